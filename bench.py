@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the SyMBA kick/encounter step on one MI355X.
+
+Headline: FP64 pair-interactions per second on the 10k cold planetesimal disk
+(N = 10000 all massive, the paper's Sec. 3 recipe, dt = 0.5 yr, critical
+radius 3 Hill radii), one step = one kick/encounter evaluation (pair forces
+over the trapezoid, encounter test over the same pairs, grouping).  The 100
+Kepler-advanced input states are resident in HBM before timing starts.
+
+Also reported: p50/p99 step latency (plain calls, one at a time), the
+64-disk batch (plain per-disk calls vs one batched launch vs the batched
+launch replayed from a captured graph), the FP64 roofline of the tile
+kernel (HIP events around it, live), and the CPU oracle timed on a bounded
+sample of the same workload.
+
+Prints one JSON line.  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR_MM = 41      # fused massive-massive pair: 25 force + 16 encounter test
+FLOP_PER_PAIR_MF = 34      # fused massive-field pair
+PEAK_FP64_VECTOR = 78.6    # TFLOP/s, MI355X: 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
+PEAK_HBM = 8000.0          # GB/s
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def percentiles(xs):
+    import numpy as np
+    a = np.asarray(xs, dtype=float)
+    return dict(p50=float(np.percentile(a, 50)), p99=float(np.percentile(a, 99)), samples=int(a.size))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in ("paper_2304_07325_amd/csrc/symba_kernels.hip", "paper_2304_07325_amd/csrc/symba_internal.h"):
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(n_tasks_per_launch_bytes=None):
+    """HBM bytes per tile-kernel launch from the committed rocprofv3 PMC summary,
+    only if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_k_tiles_disk10k.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(disk, n_m, dt, f, budget_s=15.0):
+    import oracle
+    from paper_2304_07325_amd import diskgen as dg
+    o = oracle.default()
+    pairs = dg.pair_count(disk.n, n_m)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        o.kick_encounter(disk.state(done), n_m, dt, f)
+        done += 1
+        if time.perf_counter() - t0 >= budget_s or done >= 100:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=pairs * done / el, unit="pair-interactions/s", cores=1, kind="oracle",
+                sample=f"{done} evaluations of the 10k disk (states 0..{done - 1}), single thread, "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-steps", type=int, default=300)
+    ap.add_argument("--batch-rounds", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--workload", default="disk10k")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2304_07325_amd import binding as B
+    from paper_2304_07325_amd import diskgen as dg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = dg.WORKLOADS[args.workload]
+    n, n_m, dt, f = w["n"], w["n_massive"], dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
+    disk = dg.make_disk(n, n_m, w["kind"], w["seed"])
+    evals = w["evals"]
+    log(f"workload {args.workload}: n={n} n_m={n_m} evals={evals}")
+    states = [B.to_device_state(disk.state(k)) for k in range(evals)]
+    pairs = dg.pair_count(n, n_m)
+    n_rows = min(n_m, n - 1)
+    n_tri = n if n_m >= n - 1 else n_m
+    mm = n_tri * (n_tri - 1) // 2 if n_m >= n - 1 else n_rows * (n_rows - 1) // 2
+    flop = FLOP_PER_PAIR_MM * mm + FLOP_PER_PAIR_MF * (pairs - mm)
+
+    ctx = B.Context(max_n=max(n, 1), max_pairs=max(16 * n, 1 << 16))
+    outs = [B.Outputs(n, max(16 * n, 1 << 16)) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+
+    for s in range(args.warmup):
+        ctx.kick_encounter(states[s % evals], n_m, dt, f, out=outs[s % 2])
+    torch.cuda.synchronize()
+    chk = outs[(args.warmup - 1) % 2].to_host() if args.warmup else None
+    if chk is not None:
+        assert chk["status"] == 0, f"status {chk['status']}"
+
+    # ---- throughput: K steps back to back, events around the tile kernel ----
+    ctx.set_option(B.OPT_TIMING, 1)
+    ctx.read_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ctx.kick_encounter(states[s % evals], n_m, dt, f, out=outs[s % 2])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tiles_ms, fin_ms, calls = ctx.read_timing()
+    ctx.set_option(B.OPT_TIMING, 0)
+    value = pairs * args.steps / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    tile_ms = tiles_ms / max(calls, 1)
+    achieved = flop / (tile_ms * 1e-3) / 1e12
+    log(f"throughput {value:.4e} pairs/s, {ms_per_step:.4f} ms/step, tile kernel {tile_ms * 1e3:.1f} us, "
+        f"finalize {1e3 * fin_ms / max(calls, 1):.1f} us")
+
+    # ---- latency: one step at a time ----
+    lat = []
+    for s in range(args.latency_steps):
+        t = time.perf_counter()
+        ctx.kick_encounter(states[s % evals], n_m, dt, f, out=outs[0])
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t))
+    latency = percentiles(lat)
+    log(f"latency p50 {latency['p50']:.4f} ms p99 {latency['p99']:.4f} ms")
+
+    batched = None
+    if not args.no_batch:
+        batched = bench_batch(args, B, dg, torch)
+
+    result = {
+        "metric": "FP64 pair-interactions/s (10k disk) + p50/p99 step latency, batched vs plain",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: cold planetesimal disk (Sec. 3 recipe), N={n}, N_m={n_m}, "
+                               f"dt=0.5 yr, rcrit=3 Hill radii, {evals} Kepler-advanced states resident in HBM",
+                   "pairs_per_step": pairs, "parallelism": "single GPU"},
+        "latency_ms": latency,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic_from_profiles(),
+                     "kernel": "k_tiles", "kernel_us": tile_ms * 1e3, "flop_per_launch": flop},
+        "batched": batched,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(disk, n_m, dt, f)
+    print(json.dumps(result), flush=True)
+    ctx.close()
+
+
+def bench_batch(args, B, dg, torch):
+    """64 disks (N log-uniform in [1000, 20000], N_m = N-1 or N/10): 64 plain
+    calls per round vs one batched launch vs the batched launch replayed from
+    a captured graph."""
+    import numpy as np
+    specs = dg.batch_sizes()
+    dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
+    states, outs = [], []
+    total_n, total_pairs = 0, 0
+    for (n, nm, seed) in specs:
+        d = dg.make_disk(n, nm, "cold", seed)
+        states.append(B.to_device_state(d.state(0)))
+        outs.append(B.Outputs(n, max(8 * n, 4096)))
+        total_n += n
+        total_pairs += dg.pair_count(n, nm)
+    cap = sum(o.pair_cap for o in outs)
+    ctx = B.Context(max_n=total_n, max_pairs=cap)
+    probs = [(st, nm, dt, f, o) for st, (n, nm, _), o in zip(states, specs, outs)]
+    rounds = args.batch_rounds
+
+    def plain_round():
+        for st, nm, _, _, o in probs:
+            ctx.kick_encounter(st, nm, dt, f, out=o)
+
+    def batch_round():
+        ctx.kick_encounter_batch(probs)
+
+    res = {"disks": len(specs), "bodies": total_n, "pairs_per_round": total_pairs}
+    for name, fn in (("plain", plain_round), ("batched", batch_round)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t))
+        el = time.perf_counter() - t0
+        res[name] = dict(disk_steps_per_s=len(specs) * rounds / el, pairs_per_s=total_pairs * rounds / el,
+                         round_latency_ms=percentiles(lat))
+        log(f"batch {name}: {res[name]['disk_steps_per_s']:.1f} disk-steps/s")
+    # graph-captured batched launch
+    try:
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            batch_round()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            ctx.kick_encounter_batch(probs, stream=s)
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(rounds):
+            t = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t))
+        el = time.perf_counter() - t0
+        res["batched_graph"] = dict(disk_steps_per_s=len(specs) * rounds / el,
+                                    pairs_per_s=total_pairs * rounds / el, round_latency_ms=percentiles(lat))
+        log(f"batch graph: {res['batched_graph']['disk_steps_per_s']:.1f} disk-steps/s")
+    except Exception as exc:  # reported, not hidden
+        res["batched_graph"] = {"error": repr(exc)}
+    ctx.close()
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * libsymba -- SyMBA's per-step pair-interaction and close-encounter path on
+ * AMD Instinct MI355X (gfx950), behind a plain C ABI.
+ *
+ * The operation (Lau & Lee, "Parallelization of the Symplectic Massive Body
+ * Algorithm (SyMBA) N-body Code", Sec. 2):
+ *   - every pair of the right-angled trapezoid {(i, j): 0 <= i < R, i < j < N},
+ *     R = min(N_m, N - 1), interacts once; massive bodies attract everything,
+ *     field particles (indices >= N_m when N_m < N - 1) feel the massive bodies
+ *     but attract nothing, and field-field pairs are never formed;
+ *   - the same pairs go through the close-encounter check;
+ *   - flagged pairs are grouped into independent encounter groups as they are
+ *     found (connected components of the flagged-pair graph).
+ *
+ * Units: G = 1; the Sun (mass 1) is implicit and excluded from N; positions
+ * are heliocentric.  Indices are 0-based.
+ *
+ * Outputs:
+ *   acc      the interaction acceleration a_k = sum over massive j != k whose
+ *            pair is in the trapezoid of m_j (x_j - x_k)/|x_j - x_k|^3;
+ *   pairs    flagged pairs (i < j) in lexicographic order;
+ *   group_id the smallest body index in k's encounter group (k if it has none);
+ *   n_groups the number of groups with at least two bodies.
+ *
+ * Encounter test on a pair (the paper names the check but gives no formula;
+ * this is the library's reading, evaluated bit-for-bit as written):
+ *   d = x_j - x_i, w = v_j - v_i componentwise;  rc_k = f * rh_k;
+ *   rc = rc_i + rc_j;  rc2 = rc * rc;
+ *   r2 = fma(dz,dz, fma(dy,dy, dx*dx));  v2 likewise from w;
+ *   vr = fma(dz,wz, fma(dy,wy, dx*wx));
+ *   flagged iff  r2 < rc2
+ *            or  fma(v2, dt*dt, fma(vr, 2*dt, r2)) < rc2
+ *            or  (vr < 0  and  -vr < v2*dt  and  fma(-vr, vr, r2*v2) < rc2*v2),
+ * i.e. the straight relative path over [0, dt] comes within rc at the start,
+ * at the end, or at an interior closest approach.  Every operation is a
+ * correctly rounded IEEE-754 binary64 operation, so any conforming
+ * implementation of the expression reproduces the flags exactly.
+ *
+ * Thread safety: a context serves one stream at a time.  Calls on different
+ * contexts are independent.
+ */
+#ifndef SYMBA_H
+#define SYMBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return and status codes. */
+#define SYMBA_OK 0
+#define SYMBA_EINVAL 1     /* null pointer, N < 1, N_m outside [0, N], dt < 0, rcrit_factor <= 0, NaN scalar */
+#define SYMBA_ENOMEM 2     /* device allocation failed */
+#define SYMBA_EDEVICE 3    /* a HIP runtime call failed */
+#define SYMBA_ETOOBIG 4    /* N above the context's max_n */
+
+/* Bits of the device-side status word (symba_out.status). */
+#define SYMBA_STATUS_CAPACITY 1   /* more flagged pairs than fit; *n_pairs holds the true count */
+#define SYMBA_STATUS_NONFINITE 2  /* an acceleration is Inf or NaN (e.g. coincident bodies) */
+
+/* Context options (symba_set_option). */
+#define SYMBA_OPT_TILE_ROWS 1   /* bodies per lane in triangle tiles: 1, 2 or 4 (0 = automatic) */
+#define SYMBA_OPT_FIELD_ROWS 2  /* field bodies per lane in massive x field tiles: 1 or 2 (0 = automatic) */
+#define SYMBA_OPT_ROTATE 3      /* lane rotation of the j-side sums: 0 = DPP, 1 = ds_bpermute */
+#define SYMBA_OPT_SCREEN 4      /* 0 = FP64 reach screen, 1 = FP32 closest-approach pre-screen */
+#define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
+
+typedef struct symba_ctx symba_ctx;
+
+/* Input state: N-element device arrays of binary64 (structure of arrays).
+ * x, y, z heliocentric positions; vx, vy, vz velocities; m masses (masses of
+ * field particles are never read); rh Hill radii (field particles normally 0).
+ * Preconditions: every value finite, |positions| < 2^200 and |velocities| <
+ * 2^200 (the kernels park padding slots at 2^300). */
+typedef struct {
+    const double *x, *y, *z;
+    const double *vx, *vy, *vz;
+    const double *m;
+    const double *rh;
+} symba_state;
+
+/* Outputs: device pointers, allocated and owned by the caller.
+ * ax, ay, az    [N]          interaction accelerations.
+ * pair_i/j      [pair_cap]   flagged pairs, lexicographic; written only when
+ *                            the count fits both pair_cap and the context's max_pairs.
+ * n_pairs       scalar       true number of flagged pairs (even when it does not fit).
+ * group_id      [N]          encounter-group label (smallest index in the group).
+ * n_groups      scalar       groups with at least two bodies.
+ * status        scalar       0 or an OR of SYMBA_STATUS_* bits.
+ * The scalars are written by the device; read them after the stream has
+ * completed.  With SYMBA_STATUS_CAPACITY set, acc, group_id and n_groups are
+ * still valid; only the pair arrays are not written. */
+typedef struct {
+    double *ax, *ay, *az;
+    int32_t *pair_i, *pair_j;
+    int64_t pair_cap;
+    int64_t *n_pairs;
+    int32_t *group_id;
+    int32_t *n_groups;
+    int32_t *status;
+} symba_out;
+
+/* One independent problem of a batch. */
+typedef struct {
+    symba_state state;
+    int64_t n, n_m;
+    double dt, rcrit_factor;
+    symba_out out;
+} symba_problem;
+
+/* Create a context on HIP device `device` able to take N <= max_n and store up
+ * to max_pairs flagged pairs (0 picks max(4*max_n, 4096)).  The context owns
+ * its device scratch; flags are reserved (pass 0).  Returns SYMBA_OK and sets
+ * *ctx, or an error code and leaves *ctx NULL. */
+int symba_ctx_create(symba_ctx **ctx, int device, int64_t max_n, int64_t max_pairs, uint32_t flags);
+
+/* Free the context and its scratch (after all work on it has completed). */
+int symba_ctx_destroy(symba_ctx *ctx);
+
+/* Set a tuning option (SYMBA_OPT_*).  Returns SYMBA_EINVAL for an unknown
+ * option or value.  Options change speed only: results are unaffected, except
+ * the FP32 pre-screen, which keeps the flags exact by an FP64 confirm. */
+int symba_set_option(symba_ctx *ctx, int option, int value);
+
+/* One kick/encounter evaluation (Sec. 2 of the paper): accelerations over the
+ * trapezoid, encounter flags over the same pairs, encounter groups.
+ * s: device input arrays of length n; n_m: massive-body count (n_m = n - 1
+ * and n_m = n both mean "all massive"); dt >= 0 the step; rcrit_factor > 0
+ * the critical radius in Hill radii; out: caller-owned device outputs;
+ * stream: a hipStream_t (NULL = default stream).  Enqueues the work and
+ * returns without waiting; host-checkable faults return an error before
+ * anything is enqueued.  Graph capture is allowed (no allocation, no host
+ * synchronisation, no memset nodes). */
+int symba_kick_encounter(symba_ctx *ctx, const symba_state *s, int64_t n, int64_t n_m,
+                         double dt, double rcrit_factor, const symba_out *out, void *stream);
+
+/* Many independent problems in one persistent launch (the paper's
+ * parameter-space scans run many simulations; Sec. 1).  Each problem's
+ * outputs are those of symba_kick_encounter on it.  The total of the n's must
+ * not exceed the context's max_n and the total pair storage is the context's
+ * max_pairs, shared in problem order.  problems: host array of n_problems. */
+int symba_kick_encounter_batch(symba_ctx *ctx, const symba_problem *problems, int32_t n_problems,
+                               void *stream);
+
+/* Kernel time of the calls made since the last read while SYMBA_OPT_TIMING
+ * was 1, from HIP events recorded on each call's stream: *tiles_ms sums the
+ * tile kernel (pair forces, encounter screen and test, grouping), *finalize_ms
+ * the two finalize kernels, *calls the number of calls timed (at most 4096 are
+ * kept).  Waits for the recorded events, then starts a new accumulation.
+ * Any output pointer may be NULL.  Do not enable timing under graph capture. */
+int symba_read_timing(symba_ctx *ctx, double *tiles_ms, double *finalize_ms, int64_t *calls);
+
+/* Static text for a code. */
+const char *symba_strerror(int code);
+
+/* Host-only helper (no device work): the task list of the folded trapezoid
+ * for n, n_m and a tile size of 64*rows bodies.  Writes up to cap tasks as
+ * (kind, a, b) triples into tasks[3*k..3*k+2] (kind 0: triangle block pair
+ * (a, b) in units of 64*rows; kind 1: field block a against all massive rows)
+ * and returns the task count, or -1 on invalid arguments. */
+int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,
+                         int64_t *tasks, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,367 @@
+// C ABI of libsymba: context, argument checks, task planning and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/symba.h"
+#include "symba_internal.h"
+
+using symba::Desc;
+
+struct symba_ctx {
+    int device = 0;
+    int64_t max_n = 0;
+    int64_t max_pairs = 0;
+    int max_problems = 0;
+    // scratch
+    int32_t *parent = nullptr;   // [max_n]
+    int32_t *touched = nullptr;  // [max_n]
+    int2 *pairs = nullptr;       // [max_pairs]
+    int32_t *rank = nullptr;     // [max_pairs]
+    unsigned long long *ctr = nullptr;  // [4 * max_problems]
+    double *partial = nullptr;
+    size_t partial_bytes = 0;
+    Desc *descs_dev = nullptr;   // [max_problems]
+    Desc *descs_pinned = nullptr;
+    std::vector<Desc> descs_last;  // what descs_dev currently holds
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+    // options
+    int opt_rows = 0, opt_field_rows = 0, opt_rotate = 0, opt_screen = 0, opt_timing = 0;
+    // timing events (SYMBA_OPT_TIMING): three per timed call
+    std::vector<hipEvent_t> events;
+    size_t timed_calls = 0;
+};
+
+namespace {
+
+constexpr int kMaxProblems = 4096;
+constexpr size_t kMaxTimedCalls = 4096;
+
+// Events for the next timed call, or null when timing is off or the pool is full.
+hipEvent_t *timing_slot(symba_ctx *c) {
+    if (!c->opt_timing || c->timed_calls >= kMaxTimedCalls) return nullptr;
+    const size_t need = 3 * (c->timed_calls + 1);
+    while (c->events.size() < need) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    hipEvent_t *ev = c->events.data() + 3 * c->timed_calls;
+    ++c->timed_calls;
+    return ev;
+}
+
+int rows_for(int64_t n_tri, int opt) {
+    if (opt) return opt;
+    if (n_tri >= 40000) return 4;
+    if (n_tri >= 3000) return 2;
+    return 1;
+}
+
+int field_rows_for(int64_t n_field, int opt) {
+    if (opt) return opt;
+    return n_field >= 200000 ? 2 : 1;
+}
+
+struct Plan {
+    int64_t n_rows, n_tri, B, n_tri_tasks, n_field_tasks, n_blk;
+    size_t partial_doubles;
+};
+
+Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
+    Plan p{};
+    p.n_rows = std::min(n_m, n - 1);
+    p.n_tri = n_m >= n - 1 ? n : n_m;
+    const int64_t S = (int64_t)rows * symba::kWave;
+    const int64_t F = (int64_t)field_rows * symba::kWave;
+    if (p.n_rows > 0) {
+        p.B = (p.n_tri + S - 1) / S;
+        p.n_tri_tasks = symba::fold_count(p.B);
+        p.n_field_tasks = (n - p.n_tri + F - 1) / F;
+    }
+    p.n_blk = (n + symba::kFinalizeThreads - 1) / symba::kFinalizeThreads;
+    p.partial_doubles = (size_t)p.B * 3 * (size_t)p.n_tri;
+    return p;
+}
+
+bool bad_scalar(double dt, double f) { return !(dt >= 0.0) || !std::isfinite(dt) || !(f > 0.0) || !std::isfinite(f); }
+
+bool bad_state(const symba_state *s) {
+    return !s || !s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m || !s->rh;
+}
+
+bool bad_out(const symba_out *o) {
+    return !o || !o->ax || !o->ay || !o->az || !o->n_pairs || !o->group_id || !o->n_groups ||
+           !o->status || o->pair_cap < 0 || (o->pair_cap > 0 && (!o->pair_i || !o->pair_j));
+}
+
+int grow_partial(symba_ctx *c, size_t doubles) {
+    const size_t bytes = std::max<size_t>(doubles * sizeof(double), 256);
+    if (bytes <= c->partial_bytes) return SYMBA_OK;
+    if (c->partial) {
+        if (hipFree(c->partial) != hipSuccess) return SYMBA_EDEVICE;
+        c->partial = nullptr;
+        c->partial_bytes = 0;
+    }
+    if (hipMalloc(&c->partial, bytes) != hipSuccess) {
+        c->partial = nullptr;
+        return SYMBA_ENOMEM;
+    }
+    c->partial_bytes = bytes;
+    return SYMBA_OK;
+}
+
+void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int64_t n_m, double dt,
+               double f, const Plan &p, int field_rows) {
+    std::memset(&d, 0, sizeof d);
+    d.x = s.x; d.y = s.y; d.z = s.z; d.vx = s.vx; d.vy = s.vy; d.vz = s.vz; d.m = s.m; d.rh = s.rh;
+    d.ax = o.ax; d.ay = o.ay; d.az = o.az;
+    d.pair_i = o.pair_i; d.pair_j = o.pair_j; d.pair_cap = o.pair_cap;
+    d.n_pairs_out = o.n_pairs; d.group_id = o.group_id; d.n_groups_out = o.n_groups; d.status_out = o.status;
+    d.n = n; d.n_rows = p.n_rows; d.n_tri = p.n_tri; d.dt = dt; d.f = f;
+    d.k15 = 1.5; d.k1875 = 1.875;
+    d.B = p.B; d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
+    d.n_blk = p.n_blk; d.field_block = (int64_t)field_rows * symba::kWave;
+    (void)n_m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *symba_strerror(int code) {
+    switch (code) {
+        case SYMBA_OK: return "ok";
+        case SYMBA_EINVAL: return "invalid argument";
+        case SYMBA_ENOMEM: return "device allocation failed";
+        case SYMBA_EDEVICE: return "HIP runtime error";
+        case SYMBA_ETOOBIG: return "problem larger than the context was created for";
+        default: return "unknown error";
+    }
+}
+
+int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pairs, uint32_t flags) {
+    if (!out) return SYMBA_EINVAL;
+    *out = nullptr;
+    if (max_n < 1 || max_pairs < 0 || flags != 0 || max_n > INT32_MAX) return SYMBA_EINVAL;
+    if (max_pairs == 0) max_pairs = std::max<int64_t>(4 * max_n, 4096);
+    if (max_pairs > INT32_MAX) return SYMBA_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SYMBA_EDEVICE;
+    symba_ctx *c = new (std::nothrow) symba_ctx();
+    if (!c) return SYMBA_ENOMEM;
+    c->device = device;
+    c->max_n = max_n;
+    c->max_pairs = max_pairs;
+    c->max_problems = kMaxProblems;
+    bool ok = hipMalloc(&c->parent, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
+              hipMalloc(&c->rank, sizeof(int32_t) * max_pairs) == hipSuccess &&
+              hipMalloc(&c->ctr, sizeof(unsigned long long) * 4 * kMaxProblems) == hipSuccess &&
+              hipMalloc(&c->descs_dev, sizeof(Desc) * kMaxProblems) == hipSuccess &&
+              hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        ok = hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+             hipMemset(c->rank, 0, sizeof(int32_t) * max_pairs) == hipSuccess &&
+             hipMemset(c->ctr, 0, sizeof(unsigned long long) * 4 * kMaxProblems) == hipSuccess &&
+             symba::launch_init_scratch(c->parent, max_n, nullptr) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        symba_ctx_destroy(c);
+        return SYMBA_ENOMEM;
+    }
+    *out = c;
+    return SYMBA_OK;
+}
+
+int symba_ctx_destroy(symba_ctx *c) {
+    if (!c) return SYMBA_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->parent);
+    (void)hipFree(c->touched);
+    (void)hipFree(c->pairs);
+    (void)hipFree(c->rank);
+    (void)hipFree(c->ctr);
+    (void)hipFree(c->partial);
+    (void)hipFree(c->descs_dev);
+    if (c->descs_pinned) (void)hipHostFree(c->descs_pinned);
+    if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    delete c;
+    return SYMBA_OK;
+}
+
+int symba_set_option(symba_ctx *c, int option, int value) {
+    if (!c) return SYMBA_EINVAL;
+    switch (option) {
+        case SYMBA_OPT_TILE_ROWS:
+            if (value != 0 && value != 1 && value != 2 && value != 4) return SYMBA_EINVAL;
+            c->opt_rows = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_FIELD_ROWS:
+            if (value != 0 && value != 1 && value != 2) return SYMBA_EINVAL;
+            c->opt_field_rows = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_ROTATE:
+            if (value != 0 && value != 1) return SYMBA_EINVAL;
+            c->opt_rotate = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_TIMING:
+            if (value != 0 && value != 1) return SYMBA_EINVAL;
+            c->opt_timing = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_SCREEN:
+            if (value != 0) return SYMBA_EINVAL;  // the FP32 pre-screen is not built yet
+            c->opt_screen = value;
+            return SYMBA_OK;
+        default:
+            return SYMBA_EINVAL;
+    }
+}
+
+int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt,
+                         double rcrit_factor, const symba_out *out, void *stream) {
+    if (!c || bad_state(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || bad_scalar(dt, rcrit_factor)) return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    const int n_tri_guess = (int)(n_m >= n - 1 ? n : n_m);
+    const int rows = rows_for(n_tri_guess, c->opt_rows);
+    const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
+    const Plan p = make_plan(n, n_m, rows, field_rows);
+    int rc = grow_partial(c, p.partial_doubles);
+    if (rc != SYMBA_OK) return rc;
+    Desc d;
+    fill_desc(d, *s, *out, n, n_m, dt, rcrit_factor, p, field_rows);
+    d.task_base = 0;
+    d.blk_base = 0;
+    d.partial = c->partial;
+    d.parent = c->parent;
+    d.touched = c->touched;
+    d.pairs = c->pairs;
+    d.pair_scratch_cap = c->max_pairs;
+    d.rank = c->rank;
+    d.ctr = c->ctr;
+    symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, 64};
+    hipError_t e = symba::launch_step(&d, nullptr, 1, d.n_tasks, p.n_blk, cfg, (hipStream_t)stream,
+                                      timing_slot(c));
+    return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
+}
+
+int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t n_problems,
+                               void *stream) {
+    if (!c || !probs || n_problems < 1 || n_problems > c->max_problems) return SYMBA_EINVAL;
+    int64_t total_n = 0, max_tri = 0;
+    for (int32_t k = 0; k < n_problems; ++k) {
+        const symba_problem &q = probs[k];
+        if (bad_state(&q.state) || bad_out(&q.out)) return SYMBA_EINVAL;
+        if (q.n < 1 || q.n_m < 0 || q.n_m > q.n || bad_scalar(q.dt, q.rcrit_factor)) return SYMBA_EINVAL;
+        total_n += q.n;
+        max_tri = std::max<int64_t>(max_tri, q.n_m >= q.n - 1 ? q.n : q.n_m);
+    }
+    if (total_n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    const int rows = rows_for(max_tri, c->opt_rows);
+    const int field_rows = field_rows_for(0, c->opt_field_rows);
+    std::vector<Desc> ds((size_t)n_problems);
+    std::vector<Plan> plans((size_t)n_problems);
+    size_t partial_total = 0;
+    int64_t task_total = 0, blk_total = 0, body_off = 0, pair_off = 0;
+    for (int32_t k = 0; k < n_problems; ++k) {
+        const symba_problem &q = probs[k];
+        plans[k] = make_plan(q.n, q.n_m, rows, field_rows);
+        partial_total += plans[k].partial_doubles;
+    }
+    int rc = grow_partial(c, partial_total);
+    if (rc != SYMBA_OK) return rc;
+    size_t partial_off = 0;
+    for (int32_t k = 0; k < n_problems; ++k) {
+        const symba_problem &q = probs[k];
+        Desc &d = ds[k];
+        fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[k], field_rows);
+        d.task_base = task_total;
+        d.blk_base = blk_total;
+        d.partial = c->partial + partial_off;
+        d.parent = c->parent + body_off;
+        d.touched = c->touched + body_off;
+        const int64_t share = std::min<int64_t>(std::max<int64_t>(q.out.pair_cap, 0), c->max_pairs - pair_off);
+        d.pairs = c->pairs + pair_off;
+        d.rank = c->rank + pair_off;
+        d.pair_scratch_cap = share;
+        d.ctr = c->ctr + 4 * (int64_t)k;
+        task_total += d.n_tasks;
+        blk_total += d.n_blk;
+        body_off += q.n;
+        pair_off += share;
+        partial_off += plans[k].partial_doubles;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const bool same = c->descs_last.size() == ds.size() &&
+                      std::memcmp(c->descs_last.data(), ds.data(), sizeof(Desc) * ds.size()) == 0;
+    if (!same) {
+        if (c->upload_pending && hipEventSynchronize(c->upload_done) != hipSuccess) return SYMBA_EDEVICE;
+        std::memcpy(c->descs_pinned, ds.data(), sizeof(Desc) * ds.size());
+        if (hipMemcpyAsync(c->descs_dev, c->descs_pinned, sizeof(Desc) * ds.size(), hipMemcpyHostToDevice,
+                           st) != hipSuccess)
+            return SYMBA_EDEVICE;
+        if (hipEventRecord(c->upload_done, st) != hipSuccess) return SYMBA_EDEVICE;
+        c->upload_pending = true;
+        c->descs_last = ds;
+    }
+    symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, n_problems > 16 ? 4 : 16};
+    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, task_total, blk_total, cfg, st,
+                                      timing_slot(c));
+    return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
+}
+
+int symba_read_timing(symba_ctx *c, double *tiles_ms, double *finalize_ms, int64_t *calls) {
+    if (!c) return SYMBA_EINVAL;
+    double t = 0.0, fz = 0.0;
+    for (size_t k = 0; k < c->timed_calls; ++k) {
+        hipEvent_t *ev = c->events.data() + 3 * k;
+        float a = 0.f, b = 0.f;
+        if (hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&a, ev[0], ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[1], ev[2]) != hipSuccess)
+            return SYMBA_EDEVICE;
+        t += a;
+        fz += b;
+    }
+    if (tiles_ms) *tiles_ms = t;
+    if (finalize_ms) *finalize_ms = fz;
+    if (calls) *calls = (int64_t)c->timed_calls;
+    c->timed_calls = 0;
+    return SYMBA_OK;
+}
+
+int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows, int64_t *tasks,
+                         int64_t cap) {
+    if (n < 1 || n_m < 0 || n_m > n || (rows != 1 && rows != 2 && rows != 4) ||
+        (field_rows != 1 && field_rows != 2) || cap < 0 || (cap > 0 && !tasks))
+        return -1;
+    const Plan p = make_plan(n, n_m, rows, field_rows);
+    const int64_t total = p.n_tri_tasks + p.n_field_tasks;
+    for (int64_t t = 0; t < std::min(total, cap); ++t) {
+        if (t < p.n_tri_tasks) {
+            int64_t I, J;
+            symba::fold_decode(p.B, t, I, J);
+            tasks[3 * t] = 0;
+            tasks[3 * t + 1] = I;
+            tasks[3 * t + 2] = J;
+        } else {
+            tasks[3 * t] = 1;
+            tasks[3 * t + 1] = t - p.n_tri_tasks;
+            tasks[3 * t + 2] = 0;
+        }
+    }
+    return total;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports what include/symba.h declares, rejects bad
+arguments before touching a device, and its folded task plan covers the
+paper's trapezoid exactly once (CPU only: no device call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_07325_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "symba.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(symba_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = declared_functions()
+    assert names, "no declarations found"
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in symba.h but not exported"
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_errors_before_any_device_work():
+    lib = B.lib()
+    assert lib.symba_ctx_create(None, 0, 100, 0, 0) == B.SYMBA_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.symba_ctx_create(ctypes.byref(h), 0, 0, 0, 0) == B.SYMBA_EINVAL
+    assert lib.symba_ctx_create(ctypes.byref(h), 0, 100, -1, 0) == B.SYMBA_EINVAL
+    assert lib.symba_ctx_create(ctypes.byref(h), 0, 100, 0, 7) == B.SYMBA_EINVAL
+    assert h.value is None
+    assert lib.symba_ctx_destroy(None) == B.SYMBA_EINVAL
+    assert lib.symba_set_option(None, B.OPT_TILE_ROWS, 2) == B.SYMBA_EINVAL
+    st = B.symba_state()
+    out = B.symba_out()
+    assert lib.symba_kick_encounter(None, ctypes.byref(st), 10, 9, 1.0, 3.0, ctypes.byref(out), None) \
+        == B.SYMBA_EINVAL
+    assert lib.symba_kick_encounter_batch(None, None, 1, None) == B.SYMBA_EINVAL
+    assert lib.symba_strerror(B.SYMBA_ETOOBIG).decode().startswith("problem larger")
+    assert lib.symba_plan_tasks(0, 0, 1, 1, None, 0) == -1
+    assert lib.symba_plan_tasks(10, 11, 1, 1, None, 0) == -1
+    assert lib.symba_plan_tasks(10, 5, 3, 1, None, 0) == -1
+
+
+def expand(tasks, n, n_m, rows, field_rows):
+    """Pairs covered by a task list, as a sorted array of i * n + j (i < j)."""
+    n_rows = min(n_m, n - 1)
+    n_tri = n if n_m >= n - 1 else n_m
+    S, F = 64 * rows, 64 * field_rows
+    keys = []
+    for kind, a, b in tasks:
+        if kind == 0:
+            bi = np.arange(a * S, min(a * S + S, n_tri))
+            bj = np.arange(b * S, min(b * S + S, n_tri))
+            I, J = np.meshgrid(bi, bj, indexing="ij")
+            I, J = I.ravel(), J.ravel()
+            if a == b:
+                keep = I < J
+                I, J = I[keep], J[keep]
+            lo, hi = np.minimum(I, J), np.maximum(I, J)
+            keys.append(lo * n + hi)
+        else:
+            f = np.arange(n_tri + a * F, min(n_tri + a * F + F, n))
+            I, J = np.meshgrid(np.arange(n_rows), f, indexing="ij")
+            keys.append(I.ravel() * n + J.ravel())
+    return np.sort(np.concatenate(keys)) if keys else np.zeros(0, np.int64)
+
+
+def trapezoid(n, n_m):
+    rows = min(n_m, n - 1)
+    out = [i * n + j for i in range(rows) for j in range(i + 1, n)]
+    return np.array(sorted(out), dtype=np.int64)
+
+
+@pytest.mark.parametrize("n,n_m", [(1, 0), (1, 1), (2, 1), (2, 2), (5, 0), (64, 63), (65, 64), (130, 130),
+                                   (300, 299), (257, 256), (700, 699), (400, 90), (333, 1), (200, 64),
+                                   (1000, 999), (900, 128)])
+@pytest.mark.parametrize("rows,field_rows", [(1, 1), (2, 1), (4, 2)])
+def test_plan_covers_trapezoid_once(n, n_m, rows, field_rows):
+    tasks = B.plan_tasks(n, n_m, rows, field_rows)
+    got = expand(tasks, n, n_m, rows, field_rows)
+    exp = trapezoid(n, n_m)
+    assert got.size == exp.size, "a pair is covered twice or not at all"
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("n", [64 * 5, 64 * 6, 64 * 7 + 3, 64 * 40])
+def test_fold_balances_block_rows(n):
+    """Every block row of the folded triangle gets the same number of tasks
+    (the triangle mapped onto a rectangle), up to the one extra task per row
+    of the first half when the block count is even."""
+    tasks = B.plan_tasks(n, n - 1, 1, 1)
+    blocks = (n + 63) // 64
+    per_row = np.bincount(tasks[tasks[:, 0] == 0][:, 1], minlength=blocks)
+    assert per_row.max() - per_row.min() <= 1
+    assert len(tasks) == blocks * (blocks + 1) // 2
