@@ -18,7 +18,7 @@ struct symba_ctx {
     int64_t max_pairs = 0;
     int max_problems = 0;
     // scratch
-    int32_t *parent = nullptr;   // [max_n]
+    int32_t *parent = nullptr;   // [max_n] union-find offsets, zero between calls
     int32_t *touched = nullptr;  // [max_n]
     int2 *pairs = nullptr;       // [max_pairs]
     int32_t *rank = nullptr;     // [max_pairs]
@@ -56,10 +56,13 @@ hipEvent_t *timing_slot(symba_ctx *c) {
     return ev;
 }
 
+// Bodies per lane of the triangle tiles: R = 1 keeps small problems spread
+// over many workgroups; larger R amortises the lane rotation and shrinks the
+// partial-sum buffer (B x 3 x N doubles, B = N / (64 R)).
 int rows_for(int64_t n_tri, int opt) {
     if (opt) return opt;
     if (n_tri >= 40000) return 4;
-    if (n_tri >= 3000) return 2;
+    if (n_tri >= 12000) return 2;
     return 1;
 }
 
@@ -84,7 +87,7 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
         p.n_tri_tasks = symba::fold_count(p.B);
         p.n_field_tasks = (n - p.n_tri + F - 1) / F;
     }
-    p.n_blk = (n + symba::kFinalizeThreads - 1) / symba::kFinalizeThreads;
+    p.n_blk = (n + symba::kFinBodies - 1) / symba::kFinBodies;
     p.partial_doubles = (size_t)p.B * 3 * (size_t)p.n_tri;
     return p;
 }
@@ -125,6 +128,7 @@ void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int
     d.n_pairs_out = o.n_pairs; d.group_id = o.group_id; d.n_groups_out = o.n_groups; d.status_out = o.status;
     d.n = n; d.n_rows = p.n_rows; d.n_tri = p.n_tri; d.dt = dt; d.f = f;
     d.k15 = 1.5; d.k1875 = 1.875;
+    d.screen_dt2 = 2.0 * (1.0 + 0x1p-20) * (dt * dt);
     d.B = p.B; d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
     d.n_blk = p.n_blk; d.field_block = (int64_t)field_rows * symba::kWave;
     (void)n_m;
@@ -167,10 +171,10 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
     if (ok) {
-        ok = hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+        ok = hipMemset(c->parent, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+             hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->rank, 0, sizeof(int32_t) * max_pairs) == hipSuccess &&
              hipMemset(c->ctr, 0, sizeof(unsigned long long) * 4 * kMaxProblems) == hipSuccess &&
-             symba::launch_init_scratch(c->parent, max_n, nullptr) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {

@@ -7,8 +7,9 @@
 namespace symba {
 
 constexpr int kWave = 64;          // wavefront width on gfx950
-constexpr int kQueueCap = 512;     // per-wave LDS queue of screen candidates (power of two)
 constexpr int kFinalizeThreads = 256;
+constexpr int kFinBodies = 32;     // bodies per finalize block
+constexpr int kFinSplit = kFinalizeThreads / kFinBodies;  // threads per body in the slot sums
 constexpr int kRankTile = 256;     // pairs per rank tile side
 
 // Per-problem view handed to the kernels: inputs, outputs, plan and scratch slices.
@@ -29,17 +30,18 @@ struct Desc {
     int64_t n_tri;   // bodies that carry mass: N if N_m >= N - 1, else N_m
     double dt, f;
     double k15, k1875;    // 1.5 and 1.875 (series coefficients of r^-3)
+    double screen_dt2;    // 2 (1 + 2^-20) dt^2, the screen's velocity term
     // plan
     int64_t B;            // triangle blocks of 64*rows bodies
     int64_t n_tri_tasks;  // folded block pairs
     int64_t n_tasks;      // triangle + field tasks
     int64_t task_base;    // first global task of this problem
     int64_t blk_base;     // first global finalize block of this problem
-    int64_t n_blk;        // finalize blocks of this problem
+    int64_t n_blk;        // finalize blocks of this problem (kFinBodies bodies each)
     int64_t field_block;  // field bodies per field task (64*field_rows)
     // scratch slices (context-owned)
     double *partial;      // [B][3][n_tri] per-slot partial sums
-    int32_t *parent;      // [n] union-find forest, identity between calls
+    int32_t *parent;      // [n] union-find forest as offsets to the parent (0 = root), zero between calls
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
     int2 *pairs;          // [pair_scratch_cap] flagged pairs as found, (min, max)
     int64_t pair_scratch_cap;
@@ -84,7 +86,5 @@ __host__ __device__ inline int64_t fold_count(int64_t B) {
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc,
                        int64_t n_tasks_total, int64_t n_blk_total, const LaunchCfg &cfg,
                        hipStream_t stream, hipEvent_t *ev);
-
-hipError_t launch_init_scratch(int32_t *parent, int64_t n, hipStream_t stream);
 
 }  // namespace symba

@@ -2,24 +2,28 @@
 //
 // One step (the paper's Sec. 2: trapezoid pair loop, close-encounter check,
 // grouping of encounter pairs) runs as three launches:
-//   k_tiles     the folded trapezoid in 64-lane tasks: FP64 pair forces, a
-//               conservative per-pair screen whose candidates are queued in
-//               LDS, the exact FP64 encounter test on the candidates, and the
-//               union of every flagged pair into a lock-free union-find;
+//   k_tiles     the folded trapezoid, one block pair per 4-wave workgroup:
+//               FP64 pair forces, a conservative per-pair screen whose
+//               candidates are queued in LDS, the exact FP64 encounter test
+//               on the candidates, and the union of every flagged pair into a
+//               lock-free union-find;
 //   k_finalize  per body: fixed-order sum of the per-task partial
 //               accelerations, group label = root of the union-find;
 //               per pair: canonical (lexicographic) position by counting;
 //   k_scatter   pairs to their canonical slots, scalar outputs, and the
 //               scratch returned to its between-calls state.
 //
-// Triangle tasks (massive x massive) are symmetric: each lane of a wave owns
-// `R` stationary bodies in registers; a 64-body j tile sits in LDS (stored
-// twice so that lane l reads entry l + t at step t without wrapping), and the
-// j-side sum of each pair travels with its j body by rotating the three
-// accumulators one lane per step, so that after 64 steps every j-side sum is
-// back in the lane that staged its body and no cross-lane reduction is
-// needed.  Field tasks (massive x field) are one-sided: the massive body is
-// broadcast from LDS to lanes that own field bodies.
+// Triangle tasks (massive x massive) are symmetric.  Each lane owns R
+// stationary bodies in registers; the streamed block (R tiles of 64 bodies)
+// sits in LDS, each tile stored twice so that lane l reads entry l + t at
+// step t without wrapping.  The j-side sum of a pair travels with its j body:
+// the three accumulators rotate one lane per step, so every lane always holds
+// the sums of the body it is paired with and no cross-lane reduction is
+// needed.  The 64 steps of a tile are split over the four waves of the
+// workgroup (16 steps each, all four holding the same stationary bodies);
+// their sums are combined through LDS in a fixed order.  Field tasks
+// (massive x field) are one-sided: massive bodies are broadcast from LDS to
+// lanes that own field bodies, the massive rows split over the four waves.
 #include "symba_internal.h"
 
 #include <float.h>
@@ -28,20 +32,65 @@
 namespace symba {
 namespace {
 
+// Occupancy targets of the tile kernel per tile size (waves per SIMD; the
+// register budget is 512/N VGPRs).  Tuning knobs.
+#ifndef SYMBA_WPE_R1
+#define SYMBA_WPE_R1 6
+#endif
+#ifndef SYMBA_WPE_R2
+#define SYMBA_WPE_R2 4
+#endif
+#ifndef SYMBA_WPE_R4
+#define SYMBA_WPE_R4 2
+#endif
+#ifndef SYMBA_ROT_UNROLL
+#define SYMBA_ROT_UNROLL 2  // unroll of the 64-step rotation loop (a tuning knob)
+#endif
+
+constexpr int kRotUnroll = SYMBA_ROT_UNROLL;
+
+constexpr int waves_per_eu(int R) { return R == 1 ? SYMBA_WPE_R1 : (R == 2 ? SYMBA_WPE_R2 : SYMBA_WPE_R4); }
 constexpr double kPadPos = 0x1p300;          // padding slots sit far away with zero mass
-constexpr double kReachMargin = 1.0 + 0x1p-20;
-constexpr int kQMask = kQueueCap - 1;
-// fewer than 64 outstanding after a step plus one step's pushes (4 slots x 64)
-static_assert(kQueueCap >= kWave * 5 && (kQueueCap & kQMask) == 0, "candidate queue too small");
+constexpr double kScreenQ = 4.0 * (1.0 + 0x1p-20);
 constexpr unsigned long long kStatusCapacity = 1;
 constexpr unsigned long long kStatusNonfinite = 2;
 
-struct __align__(16) TileLds {
-    double x[2 * kWave], y[2 * kWave], z[2 * kWave], m[2 * kWave], reach[2 * kWave];
-    uint2 queue[kQueueCap];
+constexpr int kTaskWaves = 4;                  // waves sharing one task
+constexpr int kTaskThreads = kTaskWaves * kWave;
+constexpr int kSteps = kWave / kTaskWaves;     // steps of each 64-step tile per wave
+
+// Workgroup LDS of a task: the streamed block (RS tiles of 64 bodies, each
+// stored twice, 16-byte pairs); after the passes the same space holds the
+// waves' partial sums [side: stationary, streamed][wave][slot][component][lane].
+template <int RS>
+struct __align__(16) TaskLds {
+    union {
+        struct {
+            double2 xy[RS][2 * kWave], zm[RS][2 * kWave], vxy[RS][2 * kWave], vzq[RS][2 * kWave];
+        } tile;
+        double comb[2][kTaskWaves][RS][3][kWave];
+    };
 };
 
+// Per-wave LDS ring of screen candidates (i, j).  After every step fewer than
+// 64 are outstanding and one step pushes at most 64 per stationary slot, so a
+// capacity of 64 (slots + 1), rounded up to a power of two, never overflows.
+struct Queue {
+    uint2 *q;
+    int mask;
+    int head, tail;
+};
+
+constexpr int queue_cap(int slots) {
+    int c = 64;
+    while (c < kWave * (slots + 1)) c *= 2;
+    return c;
+}
+
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// Index of this wave in its workgroup, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 
 // Set bits of `mask` below this lane.
 __device__ __forceinline__ int prefix_count(unsigned long long mask) {
@@ -63,15 +112,18 @@ __device__ __forceinline__ double inv_r3(double r2, double k15, double k1875) {
     return __builtin_fma(a * e, k1875, __builtin_fma(a, k15, y3));
 }
 
-// Upper bound on how close a body's pairs can come within one step:
-// (|f rh| + |v| dt)(1 + 2^-20).  A pair whose separation is at least the sum
-// of the two bodies' reaches cannot be flagged by the encounter test; the
-// margin dominates every rounding error of both the bound and the test.
-__device__ __forceinline__ double reach_of(double vx, double vy, double vz, double rh, double f,
-                                           double dt) {
-    const double sp = sqrt(__builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx)));
-    const double r = (fabs(f * rh) + sp * dt) * kReachMargin;
-    return (r <= DBL_MAX) ? r : INFINITY;  // NaN or Inf: every pair becomes a candidate
+// Screen: a pair can be flagged by the encounter test only if its separation
+// rho satisfies rho < (rc + |w| dt)(1 + 5e-8), w the relative velocity (each
+// clause of the test, with every rounding error bounded, implies it).  Since
+// (rc_i + rc_j + |w| dt)^2 <= 4 rc_i^2 + 4 rc_j^2 + 2 |w|^2 dt^2, a pair with
+//   r2 >= (1 + 2^-20) (4 rc_i^2 + 4 rc_j^2 + 2 |w|^2 dt^2)
+// is certainly not flagged.  Each body carries q = 4 (1 + 2^-20) rc^2 and the
+// kernel gets D = 2 (1 + 2^-20) dt^2; the margin dominates all rounding.  A NaN
+// anywhere makes the pair a candidate, so the exact test decides it.
+__device__ __forceinline__ bool screen(double r2, double wx, double wy, double wz, double qi,
+                                       double qj, double D) {
+    const double v2 = __builtin_fma(wz, wz, __builtin_fma(wy, wy, wx * wx));
+    return !(r2 >= __builtin_fma(v2, D, qi + qj));
 }
 
 // The library's encounter test, operation for operation as documented in
@@ -92,37 +144,40 @@ __device__ __forceinline__ bool encounter_test(double dx, double dy, double dz, 
     return start || end || inner;
 }
 
+// The union-find forest is stored as offsets to the parent: up[x] = x - parent(x),
+// 0 for a root.  All-zero is the empty forest whatever slice of the scratch a
+// problem is given, so the between-calls state needs no per-slice setup.
 __device__ __forceinline__ int uf_load(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of x.  Parents only ever decrease (parent[v] <= v), so every value
-// read is an ancestor and the walk ends at a root.
-__device__ __forceinline__ int uf_find(int32_t *parent, int x) {
-    int p = uf_load(parent + x);
-    while (p != x) {
-        x = p;
-        p = uf_load(parent + x);
+// Root of x.  Parents only ever decrease, so every offset read is positive and
+// points at an ancestor; x strictly decreases and the walk ends at a root.
+// An offset outside (0, x] cannot occur and stops the walk.
+__device__ __forceinline__ int uf_find(int32_t *up, int x) {
+    while (true) {
+        const int off = uf_load(up + x);
+        if (off <= 0 || off > x) return x;
+        x -= off;
     }
-    return x;
 }
 
-// Lock-free union: hook the larger root under the smaller one with a CAS and
-// retry if another lane or wave re-hooked it first.  Each root stays the
-// minimum of its tree, so the final roots are the component minima whatever
-// the interleaving.
-__device__ __forceinline__ void uf_unite(int32_t *parent, int a, int b) {
+// Lock-free union: hook the larger root under the smaller one with a CAS on
+// its (zero) offset and retry if another lane or wave re-hooked it first.  A
+// root stays the minimum of its tree, so the final roots are the component
+// minima whatever the interleaving.
+__device__ __forceinline__ void uf_unite(int32_t *up, int a, int b) {
     while (true) {
-        a = uf_find(parent, a);
-        b = uf_find(parent, b);
+        a = uf_find(up, a);
+        b = uf_find(up, b);
         if (a == b) return;
         if (a > b) {
             const int t = a;
             a = b;
             b = t;
         }
-        int expected = b;
-        if (__hip_atomic_compare_exchange_strong(parent + b, &expected, a, __ATOMIC_RELAXED,
+        int expected = 0;
+        if (__hip_atomic_compare_exchange_strong(up + b, &expected, b - a, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;
     }
@@ -130,12 +185,12 @@ __device__ __forceinline__ void uf_unite(int32_t *parent, int a, int b) {
 
 // Exact test of up to 64 queued candidates, one per lane; flagged pairs are
 // appended (wave ballot + prefix, one atomic per wave) and grouped at once.
-__device__ __forceinline__ void drain(const Desc &d, const TileLds &L, int head, int count) {
+__device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
     const int l = lane();
     bool flag = false;
     int a = 0, b = 0;
     if (l < count) {
-        const uint2 c = L.queue[(head + l) & kQMask];
+        const uint2 c = Q.q[(head + l) & Q.mask];
         const int i = (int)c.x, j = (int)c.y;
         if (i < d.n && j < d.n)
             flag = encounter_test(d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i],
@@ -161,68 +216,85 @@ __device__ __forceinline__ void drain(const Desc &d, const TileLds &L, int head,
 }
 
 // Append this lane's candidate (i, j) if `c`; the mask is the wave's ballot of c.
-__device__ __forceinline__ void push(TileLds &L, int &tail, unsigned long long mask, bool c,
-                                     int64_t i, int64_t j) {
-    if (c) L.queue[(tail + prefix_count(mask)) & kQMask] = make_uint2((unsigned)i, (unsigned)j);
-    tail += __popcll(mask);
+__device__ __forceinline__ void push(Queue &Q, unsigned long long mask, bool c, int64_t i, int64_t j) {
+    if (c) Q.q[(Q.tail + prefix_count(mask)) & Q.mask] = make_uint2((unsigned)i, (unsigned)j);
+    Q.tail += __popcll(mask);
 }
 
 // Keeps fewer than 64 candidates outstanding after every step, so one step's
 // pushes (at most 64 per slot) always fit the queue.
-__device__ __forceinline__ void maybe_drain(const Desc &d, TileLds &L, int &head, int tail) {
-    if (tail - head >= kWave) {
-        __syncthreads();
+// Orders LDS accesses between the lanes of one wave (the queue is private to
+// its wave, so no workgroup barrier is involved).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void maybe_drain(const Desc &d, Queue &Q) {
+    if (Q.tail - Q.head >= kWave) {
+        wave_sync();
         do {
-            drain(d, L, head, kWave);
-            head += kWave;
-        } while (tail - head >= kWave);
-        __syncthreads();
+            drain(d, Q, Q.head, kWave);
+            Q.head += kWave;
+        } while (Q.tail - Q.head >= kWave);
+        wave_sync();
     }
 }
 
-__device__ __forceinline__ void drain_rest(const Desc &d, TileLds &L, int &head, int tail) {
-    __syncthreads();
-    while (tail - head > 0) {
-        const int c = (tail - head) < kWave ? (tail - head) : kWave;
-        drain(d, L, head, c);
-        head += c;
+__device__ __forceinline__ void drain_rest(const Desc &d, Queue &Q) {
+    wave_sync();
+    while (Q.tail - Q.head > 0) {
+        const int c = (Q.tail - Q.head) < kWave ? (Q.tail - Q.head) : kWave;
+        drain(d, Q, Q.head, c);
+        Q.head += c;
     }
 }
 
-// Stage bodies [j0, j0 + 64) (entries past `limit` become padding) into the
-// LDS tile, each stored at l and l + 64.
-__device__ __forceinline__ void stage(const Desc &d, TileLds &L, int64_t j0, int64_t limit) {
-    const int l = lane();
-    const int64_t j = j0 + l;
-    double x = kPadPos, y = 0.0, z = 0.0, m = 0.0, r = 0.0;
-    if (j < limit) {
-        x = d.x[j];
-        y = d.y[j];
-        z = d.z[j];
-        m = d.m[j];
-        r = reach_of(d.vx[j], d.vy[j], d.vz[j], d.rh[j], d.f, d.dt);
-    }
-    __syncthreads();
-    L.x[l] = x; L.x[l + kWave] = x;
-    L.y[l] = y; L.y[l + kWave] = y;
-    L.z[l] = z; L.z[l + kWave] = z;
-    L.m[l] = m; L.m[l + kWave] = m;
-    L.reach[l] = r; L.reach[l + kWave] = r;
-    __syncthreads();
-}
+// One body as the tile kernel uses it; q is the screen's 4 (1 + 2^-20) (f rh)^2.
+struct Body {
+    double x, y, z, m, vx, vy, vz, q;
+};
 
-__device__ __forceinline__ void load_body(const Desc &d, int64_t k, int64_t limit, double &x,
-                                          double &y, double &z, double &m, double &r) {
+__device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
+    Body b;
     if (k < limit) {
-        x = d.x[k];
-        y = d.y[k];
-        z = d.z[k];
-        m = d.m[k];
-        r = reach_of(d.vx[k], d.vy[k], d.vz[k], d.rh[k], d.f, d.dt);
-    } else {
-        x = kPadPos;
-        y = z = m = r = 0.0;
+        b.x = d.x[k];
+        b.y = d.y[k];
+        b.z = d.z[k];
+        b.m = d.m[k];
+        b.vx = d.vx[k];
+        b.vy = d.vy[k];
+        b.vz = d.vz[k];
+        const double rc = d.f * d.rh[k];
+        b.q = kScreenQ * (rc * rc);
+    } else {  // padding: far away, massless, at rest
+        b.x = kPadPos;
+        b.y = b.z = b.m = b.vx = b.vy = b.vz = b.q = 0.0;
     }
+    return b;
+}
+
+// Stage bodies [j0, j0 + 64 nq) (entries past `limit` become padding) into
+// tiles 0..nq-1 of the workgroup's LDS, each entry also at +64.  All threads
+// of the workgroup take part; the caller brackets it with barriers.
+template <int RS>
+__device__ __forceinline__ void stage(const Desc &d, TaskLds<RS> &L, int64_t j0, int nq, int64_t limit) {
+    for (int e = threadIdx.x; e < nq * kWave; e += kTaskThreads) {
+        const Body b = load_body(d, j0 + e, limit);
+        const int q = e / kWave, jj = e % kWave;
+        L.tile.xy[q][jj] = L.tile.xy[q][jj + kWave] = make_double2(b.x, b.y);
+        L.tile.zm[q][jj] = L.tile.zm[q][jj + kWave] = make_double2(b.z, b.m);
+        L.tile.vxy[q][jj] = L.tile.vxy[q][jj + kWave] = make_double2(b.vx, b.vy);
+        L.tile.vzq[q][jj] = L.tile.vzq[q][jj + kWave] = make_double2(b.vz, b.q);
+    }
+}
+
+template <int RS>
+__device__ __forceinline__ Body tile_body(const TaskLds<RS> &L, int q, int idx) {
+    const double2 a = L.tile.xy[q][idx], b = L.tile.zm[q][idx], c = L.tile.vxy[q][idx],
+                  e = L.tile.vzq[q][idx];
+    return Body{a.x, a.y, b.x, b.y, c.x, c.y, e.x, e.y};
 }
 
 __device__ __forceinline__ double rotate_dpp(double v) {
@@ -242,7 +314,7 @@ __device__ __forceinline__ double rotate_bperm(double v, int addr) {
 
 template <int R>
 struct Slots {
-    double x[R], y[R], z[R], m[R], r[R];
+    Body b[R];
     double ax[R], ay[R], az[R];
 };
 
@@ -256,49 +328,63 @@ __device__ __forceinline__ void write_partial(const Desc &d, int64_t slot, int64
     }
 }
 
-// 64 rotation steps of one staged j tile against the first NACT slots: both
-// sides of every pair are accumulated; returns the j-side sums home.
-template <int R, int NACT, int ROT>
-__device__ __forceinline__ void rotation_pass(const Desc &d, TileLds &L, Slots<R> &S, int64_t ib, int64_t js,
-                              int &head, int &tail, double &ajx, double &ajy, double &ajz) {
+// Screen of the pairs of step t (tile entry l + t) against the first NACT
+// slots, pushing the candidates.  Used to revisit the rare steps that had one;
+// it repeats the hot loop's screen operation for operation.
+template <int R, int RS, int NACT>
+__device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, int q, const Slots<R> &S,
+                                          int64_t ib, int64_t js, int t, Queue &Q) {
+    const int l = lane();
+    const Body J = tile_body(L, q, l + t);
+    const int64_t j = js + ((l + t) & (kWave - 1));
+#pragma unroll
+    for (int r = 0; r < NACT; ++r) {
+        const Body &I = S.b[r];
+        const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const bool c = screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
+        const unsigned long long mask = __ballot(c);
+        if (mask) push(Q, mask, c, ib + r * kWave + l, j);
+    }
+    maybe_drain(d, Q);
+}
+
+// This wave's 16 steps [t0, t0 + 16) of tile q against the first NACT slots:
+// both sides of every pair are accumulated.  Lane l starts with the sums of
+// tile entry (l + t0) mod 64 and ends with those of entry (l + t0 + 16) mod 64.
+// Steps whose screen passed anywhere in the wave are only marked in a scalar
+// bit mask; the candidates are pushed afterwards (no branch in the loop).
+template <int R, int RS, int NACT, int ROT>
+__device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> &L, int q, Slots<R> &S,
+                                               int64_t ib, int64_t js, int t0, Queue &Q, double &ajx,
+                                               double &ajy, double &ajz) {
     const int l = lane();
     const int baddr = ((l + 1) & (kWave - 1)) << 2;
     ajx = ajy = ajz = 0.0;
-#pragma unroll 2
-    for (int t = 0; t < kWave; ++t) {
-        const int idx = l + t;
-        const double xj = L.x[idx], yj = L.y[idx], zj = L.z[idx], mj = L.m[idx], rj = L.reach[idx];
-        bool cand[R];
-        unsigned long long mask[R];
+    unsigned pending = 0;
+    Body Jn = tile_body(L, q, l + t0);
+#pragma unroll kRotUnroll
+    for (int u = 0; u < kSteps; ++u) {
+        const Body J = Jn;
+        Jn = tile_body(L, q, l + t0 + u + 1);  // one step ahead: the LDS latency hides behind this step
         unsigned long long any = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cand[r] = false;
-            mask[r] = 0;
-            if (r < NACT) {
-                const double dx = xj - S.x[r], dy = yj - S.y[r], dz = zj - S.z[r];
-                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const double q = inv_r3(r2, d.k15, d.k1875);
-                const double fi = mj * q, fj = S.m[r] * q;
-                S.ax[r] = __builtin_fma(fi, dx, S.ax[r]);
-                S.ay[r] = __builtin_fma(fi, dy, S.ay[r]);
-                S.az[r] = __builtin_fma(fi, dz, S.az[r]);
-                ajx = __builtin_fma(-fj, dx, ajx);
-                ajy = __builtin_fma(-fj, dy, ajy);
-                ajz = __builtin_fma(-fj, dz, ajz);
-                const double rs = S.r[r] + rj;
-                cand[r] = r2 < rs * rs;
-                mask[r] = __ballot(cand[r]);
-                any |= mask[r];
-            }
+        for (int r = 0; r < NACT; ++r) {
+            const Body &I = S.b[r];
+            const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double qf = inv_r3(r2, d.k15, d.k1875);
+            const double fi = J.m * qf, fj = I.m * qf;
+            S.ax[r] = __builtin_fma(fi, dx, S.ax[r]);
+            S.ay[r] = __builtin_fma(fi, dy, S.ay[r]);
+            S.az[r] = __builtin_fma(fi, dz, S.az[r]);
+            ajx = __builtin_fma(-fj, dx, ajx);
+            ajy = __builtin_fma(-fj, dy, ajy);
+            ajz = __builtin_fma(-fj, dz, ajz);
+            any |= __builtin_amdgcn_ballot_w64(
+                screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2));
         }
-        if (any) {
-            const int64_t j = js + ((l + t) & (kWave - 1));
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (r < NACT && mask[r]) push(L, tail, mask[r], cand[r], ib + r * kWave + l, j);
-            maybe_drain(d, L, head, tail);
-        }
+        pending |= (any != 0 ? 1u : 0u) << u;
         if (ROT == 0) {
             ajx = rotate_dpp(ajx);
             ajy = rotate_dpp(ajy);
@@ -309,134 +395,205 @@ __device__ __forceinline__ void rotation_pass(const Desc &d, TileLds &L, Slots<R
             ajz = rotate_bperm(ajz, baddr);
         }
     }
+    while (pending) {
+        const int u = __builtin_ctz(pending);
+        pending &= pending - 1;
+        push_step<R, RS, NACT>(d, L, q, S, ib, js, t0 + u, Q);
+    }
 }
 
-// Slot Q against its own 64-body tile (a diagonal sub-block): each unordered
-// pair is met from both ends, only the stationary side is accumulated, and the
-// pair is screened once (from the lane whose partner is 1..31 steps ahead, or
-// 32 steps ahead for the lower half of the wave).
-template <int R, int Q>
-__device__ __forceinline__ void diagonal_pass(const Desc &d, TileLds &L, Slots<R> &S, int64_t ib, int &head,
-                              int &tail) {
+// Slot QS against its own tile (a diagonal sub-block), this wave's steps of
+// 1..63: each unordered pair is met from both ends, only the stationary side
+// is accumulated, and the pair is screened once (from the lane whose partner
+// is 1..31 steps ahead, or 32 steps ahead for the lower half of the wave).
+template <int R, int RS, int QS>
+__device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> &L, Slots<R> &S,
+                                               int64_t ib, int t0, Queue &Q) {
     const int l = lane();
-    for (int t = 1; t < kWave; ++t) {
-        const int idx = l + t;
-        const double xj = L.x[idx], yj = L.y[idx], zj = L.z[idx], mj = L.m[idx], rj = L.reach[idx];
-        const double dx = xj - S.x[Q], dy = yj - S.y[Q], dz = zj - S.z[Q];
+    unsigned pending = 0;
+    for (int t = (t0 > 0 ? t0 : 1); t < t0 + kSteps; ++t) {
+        const Body J = tile_body(L, QS, l + t);
+        const Body &I = S.b[QS];
+        const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const double fi = mj * inv_r3(r2, d.k15, d.k1875);
-        S.ax[Q] = __builtin_fma(fi, dx, S.ax[Q]);
-        S.ay[Q] = __builtin_fma(fi, dy, S.ay[Q]);
-        S.az[Q] = __builtin_fma(fi, dz, S.az[Q]);
-        const double rs = S.r[Q] + rj;
+        const double fi = J.m * inv_r3(r2, d.k15, d.k1875);
+        S.ax[QS] = __builtin_fma(fi, dx, S.ax[QS]);
+        S.ay[QS] = __builtin_fma(fi, dy, S.ay[QS]);
+        S.az[QS] = __builtin_fma(fi, dz, S.az[QS]);
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
-        const bool c = owner && (r2 < rs * rs);
+        const bool c = owner && screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
+        pending |= (__builtin_amdgcn_ballot_w64(c) != 0 ? 1u : 0u) << (t - t0);
+    }
+    while (pending) {
+        const int t = t0 + __builtin_ctz(pending);
+        pending &= pending - 1;
+        const Body J = tile_body(L, QS, l + t);
+        const Body &I = S.b[QS];
+        const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
+        const bool c = owner && screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
         const unsigned long long mask = __ballot(c);
-        if (mask) {
-            push(L, tail, mask, c, ib + Q * kWave + l, ib + Q * kWave + ((l + t) & (kWave - 1)));
-            maybe_drain(d, L, head, tail);
-        }
+        if (mask) push(Q, mask, c, ib + QS * kWave + l, ib + QS * kWave + ((l + t) & (kWave - 1)));
+        maybe_drain(d, Q);
     }
 }
 
-template <int R, int ROT, int Q>
-__device__ __forceinline__ void diagonal_subtiles(const Desc &d, TileLds &L, Slots<R> &S, int64_t ib, int &head,
-                                  int &tail) {
-    if constexpr (Q < R) {
-        stage(d, L, ib + Q * kWave, d.n_tri);
-        if constexpr (Q > 0) {
-            double ajx, ajy, ajz;
-            rotation_pass<R, Q, ROT>(d, L, S, ib, ib + Q * kWave, head, tail, ajx, ajy, ajz);
-            S.ax[Q] += ajx;
-            S.ay[Q] += ajy;
-            S.az[Q] += ajz;
-        }
-        diagonal_pass<R, Q>(d, L, S, ib, head, tail);
-        diagonal_subtiles<R, ROT, Q + 1>(d, L, S, ib, head, tail);
+template <int R, int RS, int ROT, int QS>
+__device__ __forceinline__ void diagonal_tiles(const Desc &d, const TaskLds<RS> &L, Slots<R> &S, int64_t ib,
+                                               int t0, Queue &Q, double (&aj)[R][3]) {
+    if constexpr (QS < R) {
+        if constexpr (QS > 0)
+            rotation_range<R, RS, QS, ROT>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0], aj[QS][1],
+                                           aj[QS][2]);
+        else
+            aj[0][0] = aj[0][1] = aj[0][2] = 0.0;
+        diagonal_range<R, RS, QS>(d, L, S, ib, t0, Q);
+        diagonal_tiles<R, RS, ROT, QS + 1>(d, L, S, ib, t0, Q, aj);
     }
 }
 
-// Block pair (I, J) of the folded triangle.  Partial sums land in slot J for
-// the stationary bodies of block I and in slot I for the bodies of block J.
-template <int R, int ROT>
-__device__ __forceinline__ void triangle_task(const Desc &d, TileLds &L, int64_t I, int64_t J) {
-    const int l = lane();
+// Block pair (I, J) of the folded triangle, by the four waves of the
+// workgroup.  Partial sums land in slot J for the stationary bodies of block
+// I and in slot I for the bodies of block J (slot I for both when I == J).
+template <int R, int RS, int ROT>
+__device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t I,
+                                              int64_t J) {
+    const int l = lane(), w = wave_id();
+    const int t0 = w * kSteps;
     const int64_t ib = I * R * kWave, jb = J * R * kWave;
     Slots<R> S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        load_body(d, ib + r * kWave + l, d.n_tri, S.x[r], S.y[r], S.z[r], S.m[r], S.r[r]);
+        S.b[r] = load_body(d, ib + r * kWave + l, d.n_tri);
         S.ax[r] = S.ay[r] = S.az[r] = 0.0;
     }
-    int head = 0, tail = 0;
+    stage(d, L, jb, R, d.n_tri);
+    __syncthreads();
+    double aj[R][3];
     if (I != J) {
-        for (int q = 0; q < R; ++q) {
-            const int64_t js = jb + q * kWave;
-            stage(d, L, js, d.n_tri);
-            double ajx, ajy, ajz;
-            rotation_pass<R, R, ROT>(d, L, S, ib, js, head, tail, ajx, ajy, ajz);
-            write_partial(d, I, js + l, ajx, ajy, ajz);
-        }
-    } else {
-        diagonal_subtiles<R, ROT, 0>(d, L, S, ib, head, tail);
-    }
-    drain_rest(d, L, head, tail);
 #pragma unroll
-    for (int r = 0; r < R; ++r) write_partial(d, J, ib + r * kWave + l, S.ax[r], S.ay[r], S.az[r]);
+        for (int q = 0; q < R; ++q)
+            rotation_range<R, RS, R, ROT>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                                          aj[q][2]);
+    } else {
+        diagonal_tiles<R, RS, ROT, 0>(d, L, S, ib, t0, Q, aj);
+    }
+    drain_rest(d, Q);
+    __syncthreads();  // every wave is done with the tiles
+    const int jend = (l + t0 + kSteps) & (kWave - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        L.comb[0][w][r][0][l] = S.ax[r];
+        L.comb[0][w][r][1][l] = S.ay[r];
+        L.comb[0][w][r][2][l] = S.az[r];
+        L.comb[1][w][r][0][jend] = aj[r][0];
+        L.comb[1][w][r][1][jend] = aj[r][1];
+        L.comb[1][w][r][2][jend] = aj[r][2];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * R * kWave; e += kTaskThreads) {
+        const int side = e / (R * kWave), idx = e % (R * kWave), r = idx / kWave, ll = idx % kWave;
+        if (I == J && side == 1) continue;
+        double sum[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = 0.0;
+            for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[side][ww][r][c][ll];
+            if (I == J)
+                for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[1][ww][r][c][ll];
+            sum[c] = v;
+        }
+        if (side == 0)
+            write_partial(d, J, ib + idx, sum[0], sum[1], sum[2]);
+        else
+            write_partial(d, I, jb + idx, sum[0], sum[1], sum[2]);
+    }
 }
 
-// Field block fb against every massive row: one-sided pairs; the field
-// bodies' accelerations are complete at the end and written directly.
-template <int RF>
-__device__ __forceinline__ void field_task(const Desc &d, TileLds &L, int64_t fb) {
-    const int l = lane();
+// Field block fb against every massive row, by the four waves of the
+// workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
+// pairs; the field accelerations are complete at the end and written directly.
+template <int RF, int RS>
+__device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb) {
+    const int l = lane(), w = wave_id();
+    const int t0 = w * kSteps;
     const int64_t f0 = d.n_tri + fb * RF * kWave;
-    double xf[RF], yf[RF], zf[RF], rf[RF], ax[RF], ay[RF], az[RF];
+    Body fbody[RF];
+    double ax[RF], ay[RF], az[RF];
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        double m;
-        load_body(d, f0 + r * kWave + l, d.n, xf[r], yf[r], zf[r], m, rf[r]);
+        fbody[r] = load_body(d, f0 + r * kWave + l, d.n);
         ax[r] = ay[r] = az[r] = 0.0;
     }
-    int head = 0, tail = 0;
-    for (int64_t s0 = 0; s0 < d.n_rows; s0 += kWave) {
-        stage(d, L, s0, d.n_rows);
-        const int nv = (d.n_rows - s0) < kWave ? (int)(d.n_rows - s0) : kWave;
-        for (int t = 0; t < nv; ++t) {
-            const double xi = L.x[t], yi = L.y[t], zi = L.z[t], mi = L.m[t], ri = L.reach[t];
-            bool cand[RF];
-            unsigned long long mask[RF];
-            unsigned long long any = 0;
+    for (int64_t s0 = 0; s0 < d.n_rows; s0 += RS * kWave) {
+        const int64_t left = d.n_rows - s0;
+        const int nq = left >= RS * kWave ? RS : (int)((left + kWave - 1) / kWave);
+        stage(d, L, s0, nq, d.n_rows);
+        __syncthreads();
+        for (int q = 0; q < nq; ++q) {
+            unsigned pending = 0;
+            for (int u = 0; u < kSteps; ++u) {
+                const int64_t row = s0 + q * kWave + t0 + u;
+                if (row >= d.n_rows) break;
+                const Body I = tile_body(L, q, t0 + u);  // the same massive body in every lane
+                unsigned long long any = 0;
 #pragma unroll
-            for (int r = 0; r < RF; ++r) {
-                const double dx = xf[r] - xi, dy = yf[r] - yi, dz = zf[r] - zi;
-                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                const double fj = mi * inv_r3(r2, d.k15, d.k1875);
-                ax[r] = __builtin_fma(-fj, dx, ax[r]);
-                ay[r] = __builtin_fma(-fj, dy, ay[r]);
-                az[r] = __builtin_fma(-fj, dz, az[r]);
-                const double rs = rf[r] + ri;
-                cand[r] = r2 < rs * rs;
-                mask[r] = __ballot(cand[r]);
-                any |= mask[r];
+                for (int r = 0; r < RF; ++r) {
+                    const Body &Fb = fbody[r];
+                    const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
+                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                    const double fj = I.m * inv_r3(r2, d.k15, d.k1875);
+                    ax[r] = __builtin_fma(-fj, dx, ax[r]);
+                    ay[r] = __builtin_fma(-fj, dy, ay[r]);
+                    az[r] = __builtin_fma(-fj, dz, az[r]);
+                    any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx - I.vx, Fb.vy - I.vy,
+                                                              Fb.vz - I.vz, I.q, Fb.q, d.screen_dt2));
+                }
+                pending |= (any != 0 ? 1u : 0u) << u;
             }
-            if (any) {
+            while (pending) {
+                const int u = __builtin_ctz(pending);
+                pending &= pending - 1;
+                const int64_t row = s0 + q * kWave + t0 + u;
+                const Body I = tile_body(L, q, t0 + u);
 #pragma unroll
-                for (int r = 0; r < RF; ++r)
-                    if (mask[r]) push(L, tail, mask[r], cand[r], s0 + t, f0 + r * kWave + l);
-                maybe_drain(d, L, head, tail);
+                for (int r = 0; r < RF; ++r) {
+                    const Body &Fb = fbody[r];
+                    const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
+                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                    const bool c = screen(r2, Fb.vx - I.vx, Fb.vy - I.vy, Fb.vz - I.vz, I.q, Fb.q,
+                                          d.screen_dt2);
+                    const unsigned long long mask = __ballot(c);
+                    if (mask) push(Q, mask, c, row, f0 + r * kWave + l);
+                }
+                maybe_drain(d, Q);
             }
         }
+        __syncthreads();  // the tiles are restaged next round
     }
-    drain_rest(d, L, head, tail);
+    drain_rest(d, Q);
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        const int64_t k = f0 + r * kWave + l;
-        if (k < d.n) {
-            d.ax[k] = ax[r];
-            d.ay[k] = ay[r];
-            d.az[k] = az[r];
+        L.comb[0][w][r][0][l] = ax[r];
+        L.comb[0][w][r][1][l] = ay[r];
+        L.comb[0][w][r][2][l] = az[r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < RF * kWave; e += kTaskThreads) {
+        const int r = e / kWave, ll = e % kWave;
+        const int64_t k = f0 + e;
+        if (k >= d.n) continue;
+        double sum[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = 0.0;
+            for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[0][ww][r][c][ll];
+            sum[c] = v;
         }
+        d.ax[k] = sum[0];
+        d.ay[k] = sum[1];
+        d.az[k] = sum[2];
     }
 }
 
@@ -454,69 +611,103 @@ __device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, boo
 }
 
 template <int R, int RF, int ROT>
-__global__ __launch_bounds__(kWave) void k_tiles(Desc inl, const Desc *descs, int n_desc) {
-    __shared__ TileLds L;
-    const int64_t t = blockIdx.x;
-    const Desc d = descs ? descs[problem_of(descs, n_desc, t, true)] : inl;
+__device__ __forceinline__ void run_task(const Desc &d, int64_t t) {
+    constexpr int RS = R > RF ? R : RF;
+    __shared__ TaskLds<RS> L;
+    __shared__ uint2 qbuf[kTaskWaves][queue_cap(RS)];
+    Queue Q{qbuf[wave_id()], queue_cap(RS) - 1, 0, 0};
     const int64_t lt = t - d.task_base;
     if (lt < d.n_tri_tasks) {
         int64_t I, J;
         fold_decode(d.B, lt, I, J);
-        triangle_task<R, ROT>(d, L, I, J);
+        triangle_task<R, RS, ROT>(d, L, Q, I, J);
     } else {
-        field_task<RF>(d, L, lt - d.n_tri_tasks);
+        field_task<RF, RS>(d, L, Q, lt - d.n_tri_tasks);
     }
 }
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(Desc inl, const Desc *descs,
-                                                                int n_desc, int64_t n_blk_total,
-                                                                int rank_per_problem) {
-    __shared__ unsigned long long keys[kRankTile];
-    const int64_t b = blockIdx.x;
+// One problem: the descriptor is a kernel argument (scalar registers).
+template <int R, int RF, int ROT>
+__global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
+void k_tiles(const Desc d) {
+    run_task<R, RF, ROT>(d, blockIdx.x);
+}
+
+// Many problems: every block finds its problem by the task bases.
+template <int R, int RF, int ROT>
+__global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
+void k_tiles_batch(const Desc *__restrict__ descs, int n_desc) {
+    const int64_t t = blockIdx.x;
+    run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, true)], t);
+}
+
+struct FinLds {
+    double part[kFinSplit][3][kFinBodies];
+    unsigned long long keys[kRankTile];
+};
+
+// Body block lb of a problem: 32 bodies, each body's slot sum split over 8
+// threads (fixed ranges, combined in a fixed order: deterministic); group
+// label = union-find root.
+__device__ __forceinline__ void finalize_bodies(FinLds &F, const Desc &d, int64_t lb) {
     const int tid = threadIdx.x;
-    if (b < n_blk_total) {
-        const Desc &d = descs ? descs[problem_of(descs, n_desc, b, false)] : inl;
-        const int64_t lb = b - d.blk_base;
-        const int64_t k = lb * kFinalizeThreads + tid;
-        bool root_of_group = false, nonfinite = false;
-        if (k < d.n) {
-            double sx = 0.0, sy = 0.0, sz = 0.0;
-            if (k < d.n_tri || d.n_rows == 0) {
-                const double *p = d.partial + k;
-                for (int64_t c = 0; c < d.B; ++c) {
-                    sx += p[(3 * c) * d.n_tri];
-                    sy += p[(3 * c + 1) * d.n_tri];
-                    sz += p[(3 * c + 2) * d.n_tri];
-                }
-                d.ax[k] = sx;
-                d.ay[k] = sy;
-                d.az[k] = sz;
-            } else {
-                sx = d.ax[k];
-                sy = d.ay[k];
-                sz = d.az[k];
-            }
-            nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
-            const int g = uf_find(d.parent, (int)k);
-            d.group_id[k] = g;
-            root_of_group = d.touched[k] && g == (int)k;
-            d.touched[k] = 0;
+    auto &part = F.part;
+    const int col = tid % kFinBodies, split = tid / kFinBodies;
+    const int64_t k = lb * kFinBodies + col;
+    const bool own_sum = k < d.n && (k < d.n_tri || d.n_rows == 0);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    if (own_sum) {
+        const int64_t per = (d.B + kFinSplit - 1) / kFinSplit;
+        const int64_t c0 = split * per;
+        const int64_t c1 = (c0 + per) < d.B ? (c0 + per) : d.B;
+        const double *p = d.partial + k;
+#pragma unroll 8
+        for (int64_t c = c0; c < c1; ++c) {
+            sx += p[(3 * c) * d.n_tri];
+            sy += p[(3 * c + 1) * d.n_tri];
+            sz += p[(3 * c + 2) * d.n_tri];
         }
-        const int groups = __syncthreads_count(root_of_group);
-        const int bad = __syncthreads_or(nonfinite);
-        if (tid == 0) {
-            if (groups) atomicAdd(d.ctr + 2, (unsigned long long)groups);
-            if (bad) atomicOr(d.ctr + 3, kStatusNonfinite);
-            if (lb == 0) *d.n_pairs_out = (int64_t)d.ctr[0];
-        }
-        return;
     }
-    // canonical order of the stored pairs: rank = number of smaller keys
-    const int64_t rb = b - n_blk_total;
-    const int p = (int)(rb / rank_per_problem);
-    if (p >= n_desc) return;
-    const int r = (int)(rb % rank_per_problem);
-    const Desc &d = descs ? descs[p] : inl;
+    part[split][0][col] = sx;
+    part[split][1][col] = sy;
+    part[split][2][col] = sz;
+    __syncthreads();
+    bool root_of_group = false, nonfinite = false;
+    if (split == 0 && k < d.n) {
+        if (own_sum) {
+            for (int s2 = 1; s2 < kFinSplit; ++s2) {
+                sx += part[s2][0][col];
+                sy += part[s2][1][col];
+                sz += part[s2][2][col];
+            }
+            d.ax[k] = sx;
+            d.ay[k] = sy;
+            d.az[k] = sz;
+        } else {  // a field body: written by its field task
+            sx = d.ax[k];
+            sy = d.ay[k];
+            sz = d.az[k];
+        }
+        nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
+        const int g = uf_find(d.parent, (int)k);
+        d.group_id[k] = g;
+        root_of_group = d.touched[k] && g == (int)k;
+        d.touched[k] = 0;
+    }
+    const int groups = __syncthreads_count(root_of_group);
+    const int bad = __syncthreads_or(nonfinite);
+    if (tid == 0) {
+        if (groups) atomicAdd(d.ctr + 2, (unsigned long long)groups);
+        if (bad) atomicOr(d.ctr + 3, kStatusNonfinite);
+        if (lb == 0) *d.n_pairs_out = (int64_t)d.ctr[0];
+    }
+}
+
+// Rank block r (of rank_per_problem) of a problem: canonical position of each
+// stored pair = number of smaller keys (i, j), counted tile by tile.
+__device__ __forceinline__ void finalize_ranks(FinLds &F, const Desc &d, int r, int rank_per_problem) {
+    const int tid = threadIdx.x;
+    unsigned long long *keys = F.keys;
     const unsigned long long found = d.ctr[0];
     const int64_t ns = (int64_t)found < d.pair_scratch_cap ? (int64_t)found : d.pair_scratch_cap;
     const int64_t side = (ns + kRankTile - 1) / kRankTile;
@@ -541,11 +732,9 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_finalize(Desc inl, const D
     }
 }
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_scatter(Desc inl, const Desc *descs,
-                                                               int n_desc) {
+__device__ __forceinline__ void scatter_block(const Desc &d) {
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x;
-    const Desc &d = descs ? descs[problem_of(descs, n_desc, b, false)] : inl;
     const int64_t lb = b - d.blk_base;
     const int64_t stride = d.n_blk * kFinalizeThreads;
     const int64_t found = *d.n_pairs_out;
@@ -561,7 +750,7 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_scatter(Desc inl, const De
             d.pair_j[r] = e.y;
         }
     }
-    for (int64_t k = lb * kFinalizeThreads + tid; k < d.n; k += stride) d.parent[k] = (int32_t)k;
+    for (int64_t k = lb * kFinalizeThreads + tid; k < d.n; k += stride) d.parent[k] = 0;
     if (lb == 0 && tid == 0) {
         *d.n_groups_out = (int32_t)d.ctr[2];
         *d.status_out = (int32_t)(d.ctr[3] | (fits ? 0ull : kStatusCapacity));
@@ -569,27 +758,57 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_scatter(Desc inl, const De
     }
 }
 
-__global__ void k_identity(int32_t *parent, int64_t n) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) parent[k] = (int32_t)k;
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const Desc d, int rank_blocks) {
+    __shared__ FinLds F;
+    const int64_t b = blockIdx.x;
+    if (b < d.n_blk)
+        finalize_bodies(F, d, b);
+    else
+        finalize_ranks(F, d, (int)(b - d.n_blk), rank_blocks);
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_batch(const Desc *__restrict__ descs,
+                                                                      int n_desc, int64_t n_blk_total,
+                                                                      int rank_per_problem) {
+    __shared__ FinLds F;
+    const int64_t b = blockIdx.x;
+    if (b < n_blk_total) {
+        const Desc &d = descs[problem_of(descs, n_desc, b, false)];
+        finalize_bodies(F, d, b - d.blk_base);
+    } else {
+        const int64_t rb = b - n_blk_total;
+        const int p = (int)(rb / rank_per_problem);
+        if (p < n_desc) finalize_ranks(F, descs[p], (int)(rb % rank_per_problem), rank_per_problem);
+    }
+}
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_scatter(const Desc d) { scatter_block(d); }
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_scatter_batch(const Desc *__restrict__ descs,
+                                                                     int n_desc) {
+    scatter_block(descs[problem_of(descs, n_desc, blockIdx.x, false)]);
 }
 
 template <int R, int RF, int ROT>
-void launch_tiles(int64_t n_tasks, const Desc &inl, const Desc *descs, int n_desc,
+void launch_tiles(int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc,
                   hipStream_t stream) {
-    hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kWave), 0, stream,
-                       inl, descs, n_desc);
+    if (descs)
+        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0,
+                           stream, descs, n_desc);
+    else
+        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream,
+                           one);
 }
 
 template <int R>
-void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &inl, const Desc *descs,
+void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &one, const Desc *descs,
                     int n_desc, hipStream_t stream) {
     if (rf == 2) {
-        if (rot) launch_tiles<R, 2, 1>(n_tasks, inl, descs, n_desc, stream);
-        else launch_tiles<R, 2, 0>(n_tasks, inl, descs, n_desc, stream);
+        if (rot) launch_tiles<R, 2, 1>(n_tasks, one, descs, n_desc, stream);
+        else launch_tiles<R, 2, 0>(n_tasks, one, descs, n_desc, stream);
     } else {
-        if (rot) launch_tiles<R, 1, 1>(n_tasks, inl, descs, n_desc, stream);
-        else launch_tiles<R, 1, 0>(n_tasks, inl, descs, n_desc, stream);
+        if (rot) launch_tiles<R, 1, 1>(n_tasks, one, descs, n_desc, stream);
+        else launch_tiles<R, 1, 0>(n_tasks, one, descs, n_desc, stream);
     }
 }
 
@@ -612,22 +831,24 @@ hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc
     }
     if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return hipErrorUnknown;
     const int64_t rank_blocks = (int64_t)cfg.rank_blocks_per_problem * n_desc;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)(n_blk_total + rank_blocks)), dim3(kFinalizeThreads),
-                       0, stream, inl, dd, n_desc, n_blk_total, cfg.rank_blocks_per_problem);
+    if (dd)
+        hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)(n_blk_total + rank_blocks)),
+                           dim3(kFinalizeThreads), 0, stream, dd, n_desc, n_blk_total,
+                           cfg.rank_blocks_per_problem);
+    else
+        hipLaunchKernelGGL(k_finalize, dim3((unsigned)(n_blk_total + rank_blocks)), dim3(kFinalizeThreads),
+                           0, stream, inl, cfg.rank_blocks_per_problem);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_blk_total), dim3(kFinalizeThreads), 0, stream, inl,
-                       dd, n_desc);
+    if (dd)
+        hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)n_blk_total), dim3(kFinalizeThreads), 0, stream,
+                           dd, n_desc);
+    else
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_blk_total), dim3(kFinalizeThreads), 0, stream, inl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev && hipEventRecord(ev[2], stream) != hipSuccess) return hipErrorUnknown;
     return hipSuccess;
-}
-
-hipError_t launch_init_scratch(int32_t *parent, int64_t n, hipStream_t stream) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_identity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, parent, n);
-    return hipGetLastError();
 }
 
 }  // namespace symba
