@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--workload", default="disk10k")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run one plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -106,6 +108,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read, {nbytes} bytes written")
+        return
     w = dg.WORKLOADS[args.workload]
     n, n_m, dt, f = w["n"], w["n_massive"], dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
     disk = dg.make_disk(n, n_m, w["kind"], w["seed"])
