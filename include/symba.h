@@ -155,10 +155,12 @@ int symba_read_timing(symba_ctx *ctx, double *tiles_ms, double *finalize_ms, int
 const char *symba_strerror(int code);
 
 /* Host-only helper (no device work): the task list of the folded trapezoid
- * for n, n_m and a tile size of 64*rows bodies.  Writes up to cap tasks as
- * (kind, a, b) triples into tasks[3*k..3*k+2] (kind 0: triangle block pair
- * (a, b) in units of 64*rows; kind 1: field block a against all massive rows)
- * and returns the task count, or -1 on invalid arguments. */
+ * for n, n_m and a tile size of 64*rows bodies, in the order a single call
+ * launches them (field blocks first, then the folded triangle's block pairs,
+ * row by row).  Writes up to cap tasks as (kind, a, b)
+ * triples into tasks[3*k..3*k+2] (kind 0: triangle block pair (a, b) in units
+ * of 64*rows; kind 1: field block a against all massive rows) and returns the
+ * task count, or -1 on invalid arguments. */
 int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,
                          int64_t *tasks, int64_t cap);
 

@@ -21,8 +21,11 @@ struct symba_ctx {
     int32_t *parent = nullptr;   // [max_n] union-find offsets, zero between calls
     int32_t *touched = nullptr;  // [max_n]
     int2 *pairs = nullptr;       // [max_pairs]
-    int32_t *rank = nullptr;     // [max_pairs]
-    unsigned long long *ctr = nullptr;  // [4 * max_problems]
+    int2 *sorted = nullptr;      // [max_pairs]
+    int32_t *bcnt = nullptr;     // [max_n]
+    int32_t *bfill = nullptr;    // [max_n]
+    int32_t *bstart = nullptr;   // [max_n + max_problems]
+    unsigned long long *ctr = nullptr;  // [kCtrSlots * max_problems]
     double *partial = nullptr;
     size_t partial_bytes = 0;
     Desc *descs_dev = nullptr;   // [max_problems]
@@ -40,6 +43,10 @@ struct symba_ctx {
 namespace {
 
 constexpr int kMaxProblems = 4096;
+// Pair-scatter blocks (final kernel) and closing blocks per problem: a single
+// call spreads them wide, a batch of many problems less so.
+constexpr int kScatterBlocks = 16, kCloseBlocks = 32;
+constexpr int kScatterBlocksBatch = 2, kCloseBlocksBatch = 2;
 constexpr size_t kMaxTimedCalls = 4096;
 
 // Events for the next timed call, or null when timing is off or the pool is full.
@@ -61,8 +68,8 @@ hipEvent_t *timing_slot(symba_ctx *c) {
 // partial-sum buffer (B x 3 x N doubles, B = N / (64 R)).
 int rows_for(int64_t n_tri, int opt) {
     if (opt) return opt;
-    if (n_tri >= 40000) return 4;
-    if (n_tri >= 12000) return 2;
+    if (n_tri >= 30000) return 4;
+    if (n_tri >= 4000) return 2;
     return 1;
 }
 
@@ -165,16 +172,20 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
     bool ok = hipMalloc(&c->parent, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
-              hipMalloc(&c->rank, sizeof(int32_t) * max_pairs) == hipSuccess &&
-              hipMalloc(&c->ctr, sizeof(unsigned long long) * 4 * kMaxProblems) == hipSuccess &&
+              hipMalloc(&c->sorted, sizeof(int2) * max_pairs) == hipSuccess &&
+              hipMalloc(&c->bcnt, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->bfill, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->bstart, sizeof(int32_t) * (max_n + kMaxProblems)) == hipSuccess &&
+              hipMalloc(&c->ctr, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
               hipMalloc(&c->descs_dev, sizeof(Desc) * kMaxProblems) == hipSuccess &&
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
     if (ok) {
         ok = hipMemset(c->parent, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
-             hipMemset(c->rank, 0, sizeof(int32_t) * max_pairs) == hipSuccess &&
-             hipMemset(c->ctr, 0, sizeof(unsigned long long) * 4 * kMaxProblems) == hipSuccess &&
+             hipMemset(c->bcnt, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+             hipMemset(c->bfill, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+             hipMemset(c->ctr, 0, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {
@@ -192,7 +203,10 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->parent);
     (void)hipFree(c->touched);
     (void)hipFree(c->pairs);
-    (void)hipFree(c->rank);
+    (void)hipFree(c->sorted);
+    (void)hipFree(c->bcnt);
+    (void)hipFree(c->bfill);
+    (void)hipFree(c->bstart);
     (void)hipFree(c->ctr);
     (void)hipFree(c->partial);
     (void)hipFree(c->descs_dev);
@@ -246,17 +260,21 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     Desc d;
     fill_desc(d, *s, *out, n, n_m, dt, rcrit_factor, p, field_rows);
     d.task_base = 0;
-    d.blk_base = 0;
     d.partial = c->partial;
     d.parent = c->parent;
     d.touched = c->touched;
     d.pairs = c->pairs;
     d.pair_scratch_cap = c->max_pairs;
-    d.rank = c->rank;
+    d.sorted = c->sorted;
+    d.bcnt = c->bcnt;
+    d.bfill = c->bfill;
+    d.bstart = c->bstart;
+    d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
-    symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, 64};
-    hipError_t e = symba::launch_step(&d, nullptr, 1, d.n_tasks, p.n_blk, cfg, (hipStream_t)stream,
-                                      timing_slot(c));
+    const symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
+    d.fin_base = 0;
+    hipError_t e = symba::launch_step(&d, nullptr, 1, d.n_tasks, symba::final_blocks(n, kScatterBlocks), cfg,
+                                      (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
 
@@ -278,7 +296,9 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     std::vector<Desc> ds((size_t)n_problems);
     std::vector<Plan> plans((size_t)n_problems);
     size_t partial_total = 0;
-    int64_t task_total = 0, blk_total = 0, body_off = 0, pair_off = 0;
+    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0;
+    const symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, kScatterBlocksBatch,
+                               kCloseBlocksBatch};
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
         plans[k] = make_plan(q.n, q.n_m, rows, field_rows);
@@ -292,17 +312,21 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         Desc &d = ds[k];
         fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[k], field_rows);
         d.task_base = task_total;
-        d.blk_base = blk_total;
         d.partial = c->partial + partial_off;
         d.parent = c->parent + body_off;
         d.touched = c->touched + body_off;
         const int64_t share = std::min<int64_t>(std::max<int64_t>(q.out.pair_cap, 0), c->max_pairs - pair_off);
         d.pairs = c->pairs + pair_off;
-        d.rank = c->rank + pair_off;
+        d.sorted = c->sorted + pair_off;
+        d.bcnt = c->bcnt + body_off;
+        d.bfill = c->bfill + body_off;
+        d.bstart = c->bstart + body_off + k;
+        d.nb = symba::bucket_count(q.n);
         d.pair_scratch_cap = share;
-        d.ctr = c->ctr + 4 * (int64_t)k;
+        d.ctr = c->ctr + symba::kCtrSlots * (int64_t)k;
+        d.fin_base = fin_total;
         task_total += d.n_tasks;
-        blk_total += d.n_blk;
+        fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);
         body_off += q.n;
         pair_off += share;
         partial_off += plans[k].partial_doubles;
@@ -320,8 +344,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         c->upload_pending = true;
         c->descs_last = ds;
     }
-    symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, n_problems > 16 ? 4 : 16};
-    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, task_total, blk_total, cfg, st,
+    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, task_total, fin_total, cfg, st,
                                       timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
@@ -352,17 +375,18 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
         return -1;
     const Plan p = make_plan(n, n_m, rows, field_rows);
     const int64_t total = p.n_tri_tasks + p.n_field_tasks;
-    for (int64_t t = 0; t < std::min(total, cap); ++t) {
+    for (int64_t f = 0; f < std::min(total, cap); ++f) {
+        const int64_t t = symba::task_in_order(p.n_tri_tasks, total, f);
         if (t < p.n_tri_tasks) {
             int64_t I, J;
             symba::fold_decode(p.B, t, I, J);
-            tasks[3 * t] = 0;
-            tasks[3 * t + 1] = I;
-            tasks[3 * t + 2] = J;
+            tasks[3 * f] = 0;
+            tasks[3 * f + 1] = I;
+            tasks[3 * f + 2] = J;
         } else {
-            tasks[3 * t] = 1;
-            tasks[3 * t + 1] = t - p.n_tri_tasks;
-            tasks[3 * t + 2] = 0;
+            tasks[3 * f] = 1;
+            tasks[3 * f + 1] = t - p.n_tri_tasks;
+            tasks[3 * f + 2] = 0;
         }
     }
     return total;

@@ -10,7 +10,14 @@ constexpr int kWave = 64;          // wavefront width on gfx950
 constexpr int kFinalizeThreads = 256;
 constexpr int kFinBodies = 32;     // bodies per finalize block
 constexpr int kFinSplit = kFinalizeThreads / kFinBodies;  // threads per body in the slot sums
-constexpr int kRankTile = 256;     // pairs per rank tile side
+constexpr int kMaxBuckets = 4096;  // index buckets of the canonical pair order
+
+// Per-problem device counters (zero between calls).
+constexpr int kCtrPairs = 0;   // flagged pairs found
+constexpr int kCtrSpare = 1;   // unused
+constexpr int kCtrGroups = 2;  // encounter groups (components with >= 2 bodies)
+constexpr int kCtrStatus = 3;  // status bits
+constexpr int kCtrSlots = 4;
 
 // Per-problem view handed to the kernels: inputs, outputs, plan and scratch slices.
 struct Desc {
@@ -36,8 +43,8 @@ struct Desc {
     int64_t n_tri_tasks;  // folded block pairs
     int64_t n_tasks;      // triangle + field tasks
     int64_t task_base;    // first global task of this problem
-    int64_t blk_base;     // first global finalize block of this problem
-    int64_t n_blk;        // finalize blocks of this problem (kFinBodies bodies each)
+    int64_t n_blk;        // body blocks of this problem's final kernel (kFinBodies bodies each)
+    int64_t fin_base;     // first global final-kernel block of this problem
     int64_t field_block;  // field bodies per field task (64*field_rows)
     // scratch slices (context-owned)
     double *partial;      // [B][3][n_tri] per-slot partial sums
@@ -45,8 +52,12 @@ struct Desc {
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
     int2 *pairs;          // [pair_scratch_cap] flagged pairs as found, (min, max)
     int64_t pair_scratch_cap;
-    int32_t *rank;        // [pair_scratch_cap] output position, zero between calls
-    unsigned long long *ctr;  // [4]: found pairs, screen candidates, groups, status bits; zero between calls
+    int2 *sorted;         // [pair_scratch_cap] flagged pairs grouped by bucket
+    int32_t *bcnt;        // [nb] flagged pairs per bucket, zero between calls
+    int32_t *bfill;       // [nb] bucket fill counters, zero between calls
+    int32_t *bstart;      // [nb + 1] bucket starts in the canonical order
+    int32_t nb;           // buckets: min(n, kMaxBuckets)
+    unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
 };
 
 struct LaunchCfg {
@@ -54,7 +65,8 @@ struct LaunchCfg {
     int field_rows;  // 1 or 2
     int rotate;      // 0 DPP, 1 ds_bpermute
     int screen;      // 0 FP64 reach screen, 1 FP32 pre-screen
-    int rank_blocks_per_problem;
+    int scatter_blocks_per_problem;  // pair-scatter blocks per problem (final kernel)
+    int close_blocks_per_problem;    // closing-kernel blocks per problem
 };
 
 // Folded triangle: task t of B blocks -> block pair (I, J); every unordered
@@ -78,13 +90,30 @@ __host__ __device__ inline int64_t fold_count(int64_t B) {
     return B * ((B - 1) / 2 + 1) + ((B % 2 == 0) ? B / 2 : 0);
 }
 
-// Launch the three kernels of one step over n_desc problems.  descs_dev is a
-// device copy of descs (may be null when n_desc == 1).
-// device copy of descs (may be null when n_desc == 1).  ev, when not null,
-// holds three events recorded before the tile kernel, after it, and after the
-// finalize kernels.
+// Order in which a single problem's tasks are launched (position f of the
+// launch order -> task index): the field tasks, which are the longest when
+// there are many massive rows, first; then the folded triangle.
+__host__ __device__ inline int64_t task_in_order(int64_t n_tri_tasks, int64_t n_tasks, int64_t f) {
+    const int64_t n_field = n_tasks - n_tri_tasks;
+    return f < n_field ? n_tri_tasks + f : f - n_field;
+}
+
+// Final-kernel blocks of a problem of n bodies: one body block per kFinBodies
+// bodies, then the pair-scatter blocks.
+inline int64_t final_blocks(int64_t n, int scatter_blocks) {
+    return (n + kFinBodies - 1) / kFinBodies + scatter_blocks;
+}
+
+inline int32_t bucket_count(int64_t n) { return (int32_t)(n < kMaxBuckets ? n : kMaxBuckets); }
+
+// Launch the three kernels of one step over n_desc problems: the tile kernel,
+// the final kernel (body sums and labels, pairs into index buckets) and the
+// closing kernel (canonical pair order, outputs, scratch reset).
+// descs_dev is a device copy of descs (may be null when n_desc == 1).  ev,
+// when not null, holds three events recorded before the tile kernel, after
+// it, and after the closing kernel.
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc,
-                       int64_t n_tasks_total, int64_t n_blk_total, const LaunchCfg &cfg,
-                       hipStream_t stream, hipEvent_t *ev);
+                       int64_t n_tasks_total, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
+                       hipEvent_t *ev);
 
 }  // namespace symba

@@ -2,16 +2,17 @@
 //
 // One step (the paper's Sec. 2: trapezoid pair loop, close-encounter check,
 // grouping of encounter pairs) runs as three launches:
-//   k_tiles     the folded trapezoid, one block pair per 4-wave workgroup:
-//               FP64 pair forces, a conservative per-pair screen whose
-//               candidates are queued in LDS, the exact FP64 encounter test
-//               on the candidates, and the union of every flagged pair into a
-//               lock-free union-find;
-//   k_finalize  per body: fixed-order sum of the per-task partial
-//               accelerations, group label = root of the union-find;
-//               per pair: canonical (lexicographic) position by counting;
-//   k_scatter   pairs to their canonical slots, scalar outputs, and the
-//               scratch returned to its between-calls state.
+//   k_tiles  the folded trapezoid, one block pair per 4-wave workgroup: FP64
+//            pair forces into per-task partial sums, a conservative per-pair
+//            screen whose candidates are queued in LDS, and, after the task's
+//            last barrier, the exact FP64 encounter test of the candidates,
+//            flagged pairs appended, counted per index bucket and united in a
+//            lock-free union-find;
+//   k_final  per body: fixed-order sum of the partial accelerations and the
+//            group label (union-find root); per pair: moved into its bucket;
+//   k_close  per pair: canonical (lexicographic) position by counting the
+//            smaller keys of its bucket, pair written out; scalar outputs;
+//            scratch returned to its between-calls state.
 //
 // Triangle tasks (massive x massive) are symmetric.  Each lane owns R
 // stationary bodies in registers; the streamed block (R tiles of 64 bodies)
@@ -52,6 +53,7 @@ constexpr int kRotUnroll = SYMBA_ROT_UNROLL;
 constexpr int waves_per_eu(int R) { return R == 1 ? SYMBA_WPE_R1 : (R == 2 ? SYMBA_WPE_R2 : SYMBA_WPE_R4); }
 constexpr double kPadPos = 0x1p300;          // padding slots sit far away with zero mass
 constexpr double kScreenQ = 4.0 * (1.0 + 0x1p-20);
+constexpr double kScreenInflate = 1.0 + 0x1p-40;
 constexpr unsigned long long kStatusCapacity = 1;
 constexpr unsigned long long kStatusNonfinite = 2;
 
@@ -92,6 +94,15 @@ __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 // Index of this wave in its workgroup, as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 
+// 1 if the wave-uniform mask is non-zero, else 0, computed by the scalar unit
+// (written out because a compare on the mask is otherwise lowered to a per-lane
+// select that is read back from a vector register).
+__device__ __forceinline__ unsigned nonzero(unsigned long long mask) {
+    unsigned r;
+    asm("s_cmp_lg_u64 %1, 0\n\ts_cselect_b32 %0, 1, 0" : "=s"(r) : "s"(mask) : "scc");
+    return r;
+}
+
 // Set bits of `mask` below this lane.
 __device__ __forceinline__ int prefix_count(unsigned long long mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
@@ -100,30 +111,36 @@ __device__ __forceinline__ int prefix_count(unsigned long long mask) {
 
 // r2^(-3/2): the hardware reciprocal-square-root estimate y (relative error
 // near 2^-23) corrected by the binomial series of (1 - e)^(-3/2), e = 1 - r2 y^2,
-// to second order: q = y^3 (1 + 3e/2 + 15e^2/8), truncation ~ (35/16) e^3.
+// to second order: q = y^3 (1 + e (3/2 + 15e/8)), truncation ~ (35/16) e^3.
 // k15 = 1.5 and k1875 = 1.875 arrive as kernel arguments so that they sit in
-// scalar registers (gfx950's VOP3 FMA takes no literal operand).
+// scalar registers (gfx950's VOP3 FMA takes no literal operand; 1.0 is an
+// inline constant).
 __device__ __forceinline__ double inv_r3(double r2, double k15, double k1875) {
     const double y = __builtin_amdgcn_rsq(r2);
     const double y2 = y * y;
     const double e = __builtin_fma(-r2, y2, 1.0);
-    const double y3 = y2 * y;
-    const double a = e * y3;
-    return __builtin_fma(a * e, k1875, __builtin_fma(a, k15, y3));
+    const double s = __builtin_fma(e, __builtin_fma(e, k1875, k15), 1.0);
+    return (y2 * y) * s;
 }
 
 // Screen: a pair can be flagged by the encounter test only if its separation
 // rho satisfies rho < (rc + |w| dt)(1 + 5e-8), w the relative velocity (each
 // clause of the test, with every rounding error bounded, implies it).  Since
 // (rc_i + rc_j + |w| dt)^2 <= 4 rc_i^2 + 4 rc_j^2 + 2 |w|^2 dt^2, a pair with
-//   r2 >= (1 + 2^-20) (4 rc_i^2 + 4 rc_j^2 + 2 |w|^2 dt^2)
-// is certainly not flagged.  Each body carries q = 4 (1 + 2^-20) rc^2 and the
-// kernel gets D = 2 (1 + 2^-20) dt^2; the margin dominates all rounding.  A NaN
-// anywhere makes the pair a candidate, so the exact test decides it.
-__device__ __forceinline__ bool screen(double r2, double wx, double wy, double wz, double qi,
-                                       double qj, double D) {
-    const double v2 = __builtin_fma(wz, wz, __builtin_fma(wy, wy, wx * wx));
-    return !(r2 >= __builtin_fma(v2, D, qi + qj));
+//   r2 >= q_i + q_j + D |v_j - v_i|^2,  q = 4 (1 + 2^-20) rc^2,  D = 2 (1 + 2^-20) dt^2
+// is certainly not flagged (the 2^-20 margin dominates every rounding error).
+// The velocity term is expanded so that a pair costs one add, three FMAs and
+// a compare:  q_i + q_j + D |v_j - v_i|^2 = Q_i + Q_j + u_i . v_j  with
+// Q = q + D |v|^2 and u = -2 D v per body.  The expanded form cancels when
+// v_i ~ v_j; its rounding error is below 16 eps (Q_i + Q_j) (|u_i . v_j| <=
+// Q_i + Q_j), so each Q is inflated by 2^-40 (Q_i + Q_j) >> 16 eps (Q_i + Q_j),
+// which keeps the computed threshold above the exact one.  A NaN anywhere
+// makes the pair a candidate, so the exact test decides it.
+// The register-side body carries u, the LDS-side body v.
+__device__ __forceinline__ bool screen(double r2, double ux, double uy, double uz, double Qi, double vx,
+                                       double vy, double vz, double Qj) {
+    const double thr = __builtin_fma(uz, vz, __builtin_fma(uy, vy, __builtin_fma(ux, vx, Qi + Qj)));
+    return !(r2 >= thr);
 }
 
 // The library's encounter test, operation for operation as documented in
@@ -151,14 +168,27 @@ __device__ __forceinline__ int uf_load(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Root of x.  Parents only ever decrease, so every offset read is positive and
-// points at an ancestor; x strictly decreases and the walk ends at a root.
-// An offset outside (0, x] cannot occur and stops the walk.
+__device__ __forceinline__ void uf_store(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x, with path halving: every other node on the walk is re-pointed at
+// its grandparent, so trees stay shallow however the unions interleave.
+// Parents only ever decrease and a grandparent is an ancestor, so every
+// offset read is positive and points at an ancestor; x strictly decreases and
+// the walk ends at a root.  Only non-roots are re-pointed (the hooking CAS
+// only ever targets roots), and an offset outside (0, x] cannot occur and
+// stops the walk.
 __device__ __forceinline__ int uf_find(int32_t *up, int x) {
     while (true) {
         const int off = uf_load(up + x);
         if (off <= 0 || off > x) return x;
-        x -= off;
+        const int p = x - off;
+        const int off2 = uf_load(up + p);
+        if (off2 <= 0 || off2 > p) return p;
+        const int g = p - off2;
+        uf_store(up + x, x - g);
+        x = g;
     }
 }
 
@@ -183,36 +213,42 @@ __device__ __forceinline__ void uf_unite(int32_t *up, int a, int b) {
     }
 }
 
-// Exact test of up to 64 queued candidates, one per lane; flagged pairs are
+// Bucket of a pair by its smaller index: nb buckets in index order, so that
+// the canonical (lexicographic) pair order is bucket by bucket.
+__device__ __forceinline__ int bucket_of(const Desc &d, int a) { return (int)(((int64_t)a * d.nb) / d.n); }
+
+// Exact test of one candidate per lane (wave-collective): flagged pairs are
 // appended (wave ballot + prefix, one atomic per wave) and grouped at once.
-__device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
-    const int l = lane();
+__device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i, int j) {
     bool flag = false;
-    int a = 0, b = 0;
-    if (l < count) {
-        const uint2 c = Q.q[(head + l) & Q.mask];
-        const int i = (int)c.x, j = (int)c.y;
-        if (i < d.n && j < d.n)
-            flag = encounter_test(d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i],
-                              d.vx[j] - d.vx[i], d.vy[j] - d.vy[i], d.vz[j] - d.vz[i],
-                              d.rh[i], d.rh[j], d.f, d.dt);
-        a = i < j ? i : j;
-        b = i < j ? j : i;
-    }
+    if (valid && i < d.n && j < d.n)
+        flag = encounter_test(d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i], d.vx[j] - d.vx[i],
+                              d.vy[j] - d.vy[i], d.vz[j] - d.vz[i], d.rh[i], d.rh[j], d.f, d.dt);
+    const int a = i < j ? i : j, b = i < j ? j : i;
     const unsigned long long fm = __ballot(flag);
-    if (l == 0) atomicAdd(d.ctr + 1, (unsigned long long)count);
     if (fm == 0) return;
     const int leader = __ffsll((long long)fm) - 1;
     unsigned long long base = 0;
-    if (l == leader) base = atomicAdd(d.ctr, (unsigned long long)__popcll(fm));
+    if (lane() == leader) base = atomicAdd(d.ctr + kCtrPairs, (unsigned long long)__popcll(fm));
+    if (flag) {  // the union does not need the slot, so it overlaps the reservation
+        d.touched[a] = 1;
+        d.touched[b] = 1;
+        atomicAdd(d.bcnt + bucket_of(d, a), 1);
+        uf_unite(d.parent, a, b);
+    }
     base = __shfl(base, leader);
     if (flag) {
         const unsigned long long pos = base + (unsigned long long)prefix_count(fm);
         if (pos < (unsigned long long)d.pair_scratch_cap) d.pairs[pos] = make_int2(a, b);
-        d.touched[a] = 1;
-        d.touched[b] = 1;
-        uf_unite(d.parent, a, b);
     }
+}
+
+// Exact test of up to 64 queued candidates, one per lane.
+__device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
+    const bool mine = lane() < count;
+    uint2 c = make_uint2(0u, 0u);
+    if (mine) c = Q.q[(head + lane()) & Q.mask];
+    test_and_group(d, mine, (int)c.x, (int)c.y);
 }
 
 // Append this lane's candidate (i, j) if `c`; the mask is the wave's ballot of c.
@@ -251,11 +287,14 @@ __device__ __forceinline__ void drain_rest(const Desc &d, Queue &Q) {
     }
 }
 
-// One body as the tile kernel uses it; q is the screen's 4 (1 + 2^-20) (f rh)^2.
+// One body as the tile kernel uses it.  An LDS-side body carries its velocity
+// in (vx, vy, vz), a register-side body the screen's u = -2 D v; Q is the
+// screen's Q = (1 + 2^-40) (4 (1 + 2^-20) (f rh)^2 + D |v|^2).
 struct Body {
-    double x, y, z, m, vx, vy, vz, q;
+    double x, y, z, m, vx, vy, vz, Q;
 };
 
+template <bool REG>
 __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
     Body b;
     if (k < limit) {
@@ -263,14 +302,18 @@ __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limi
         b.y = d.y[k];
         b.z = d.z[k];
         b.m = d.m[k];
-        b.vx = d.vx[k];
-        b.vy = d.vy[k];
-        b.vz = d.vz[k];
+        const double vx = d.vx[k], vy = d.vy[k], vz = d.vz[k];
         const double rc = d.f * d.rh[k];
-        b.q = kScreenQ * (rc * rc);
+        const double D = d.screen_dt2;
+        const double v2 = __builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx));
+        b.Q = kScreenInflate * __builtin_fma(D, v2, kScreenQ * (rc * rc));
+        const double s = REG ? -2.0 * D : 1.0;
+        b.vx = s * vx;
+        b.vy = s * vy;
+        b.vz = s * vz;
     } else {  // padding: far away, massless, at rest
         b.x = kPadPos;
-        b.y = b.z = b.m = b.vx = b.vy = b.vz = b.q = 0.0;
+        b.y = b.z = b.m = b.vx = b.vy = b.vz = b.Q = 0.0;
     }
     return b;
 }
@@ -281,12 +324,12 @@ __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limi
 template <int RS>
 __device__ __forceinline__ void stage(const Desc &d, TaskLds<RS> &L, int64_t j0, int nq, int64_t limit) {
     for (int e = threadIdx.x; e < nq * kWave; e += kTaskThreads) {
-        const Body b = load_body(d, j0 + e, limit);
+        const Body b = load_body<false>(d, j0 + e, limit);
         const int q = e / kWave, jj = e % kWave;
         L.tile.xy[q][jj] = L.tile.xy[q][jj + kWave] = make_double2(b.x, b.y);
         L.tile.zm[q][jj] = L.tile.zm[q][jj + kWave] = make_double2(b.z, b.m);
         L.tile.vxy[q][jj] = L.tile.vxy[q][jj + kWave] = make_double2(b.vx, b.vy);
-        L.tile.vzq[q][jj] = L.tile.vzq[q][jj + kWave] = make_double2(b.vz, b.q);
+        L.tile.vzq[q][jj] = L.tile.vzq[q][jj + kWave] = make_double2(b.vz, b.Q);
     }
 }
 
@@ -342,7 +385,7 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
         const Body &I = S.b[r];
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const bool c = screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
+        const bool c = screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
         const unsigned long long mask = __ballot(c);
         if (mask) push(Q, mask, c, ib + r * kWave + l, j);
     }
@@ -382,9 +425,9 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
             ajy = __builtin_fma(-fj, dy, ajy);
             ajz = __builtin_fma(-fj, dz, ajz);
             any |= __builtin_amdgcn_ballot_w64(
-                screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2));
+                screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q));
         }
-        pending |= (any != 0 ? 1u : 0u) << u;
+        pending |= nonzero(any) << u;
         if (ROT == 0) {
             ajx = rotate_dpp(ajx);
             ajy = rotate_dpp(ajy);
@@ -421,8 +464,8 @@ __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> 
         S.ay[QS] = __builtin_fma(fi, dy, S.ay[QS]);
         S.az[QS] = __builtin_fma(fi, dz, S.az[QS]);
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
-        const bool c = owner && screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
-        pending |= (__builtin_amdgcn_ballot_w64(c) != 0 ? 1u : 0u) << (t - t0);
+        const bool c = owner && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+        pending |= nonzero(__builtin_amdgcn_ballot_w64(c)) << (t - t0);
     }
     while (pending) {
         const int t = t0 + __builtin_ctz(pending);
@@ -432,7 +475,7 @@ __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> 
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
-        const bool c = owner && screen(r2, J.vx - I.vx, J.vy - I.vy, J.vz - I.vz, I.q, J.q, d.screen_dt2);
+        const bool c = owner && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
         const unsigned long long mask = __ballot(c);
         if (mask) push(Q, mask, c, ib + QS * kWave + l, ib + QS * kWave + ((l + t) & (kWave - 1)));
         maybe_drain(d, Q);
@@ -465,7 +508,7 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     Slots<R> S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        S.b[r] = load_body(d, ib + r * kWave + l, d.n_tri);
+        S.b[r] = load_body<true>(d, ib + r * kWave + l, d.n_tri);
         S.ax[r] = S.ay[r] = S.az[r] = 0.0;
     }
     stage(d, L, jb, R, d.n_tri);
@@ -479,7 +522,6 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     } else {
         diagonal_tiles<R, RS, ROT, 0>(d, L, S, ib, t0, Q, aj);
     }
-    drain_rest(d, Q);
     __syncthreads();  // every wave is done with the tiles
     const int jend = (l + t0 + kSteps) & (kWave - 1);
 #pragma unroll
@@ -509,6 +551,10 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
         else
             write_partial(d, I, jb + idx, sum[0], sum[1], sum[2]);
     }
+    // The candidates left in this wave's queue are tested last, after the
+    // workgroup's barriers, so the other waves never wait on the test's
+    // memory round trips.
+    drain_rest(d, Q);
 }
 
 // Field block fb against every massive row, by the four waves of the
@@ -523,7 +569,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
     double ax[RF], ay[RF], az[RF];
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        fbody[r] = load_body(d, f0 + r * kWave + l, d.n);
+        fbody[r] = load_body<true>(d, f0 + r * kWave + l, d.n);
         ax[r] = ay[r] = az[r] = 0.0;
     }
     for (int64_t s0 = 0; s0 < d.n_rows; s0 += RS * kWave) {
@@ -547,10 +593,9 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
                     ax[r] = __builtin_fma(-fj, dx, ax[r]);
                     ay[r] = __builtin_fma(-fj, dy, ay[r]);
                     az[r] = __builtin_fma(-fj, dz, az[r]);
-                    any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx - I.vx, Fb.vy - I.vy,
-                                                              Fb.vz - I.vz, I.q, Fb.q, d.screen_dt2));
+                    any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q));
                 }
-                pending |= (any != 0 ? 1u : 0u) << u;
+                pending |= nonzero(any) << u;
             }
             while (pending) {
                 const int u = __builtin_ctz(pending);
@@ -562,8 +607,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
                     const Body &Fb = fbody[r];
                     const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
                     const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const bool c = screen(r2, Fb.vx - I.vx, Fb.vy - I.vy, Fb.vz - I.vz, I.q, Fb.q,
-                                          d.screen_dt2);
+                    const bool c = screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q);
                     const unsigned long long mask = __ballot(c);
                     if (mask) push(Q, mask, c, row, f0 + r * kWave + l);
                 }
@@ -572,7 +616,6 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         }
         __syncthreads();  // the tiles are restaged next round
     }
-    drain_rest(d, Q);
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
         L.comb[0][w][r][0][l] = ax[r];
@@ -595,13 +638,16 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         d.ay[k] = sum[1];
         d.az[k] = sum[2];
     }
+    drain_rest(d, Q);  // after the barriers, as in the triangle tasks
 }
 
-__device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, bool by_task) {
+// Problem owning global index `key` of the task list (which 0) or of the
+// final-kernel blocks (which 1): the last problem whose base is not above it.
+__device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, int which) {
     int lo = 0, hi = n_desc - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t base = by_task ? descs[mid].task_base : descs[mid].blk_base;
+        const int64_t base = which == 0 ? descs[mid].task_base : descs[mid].fin_base;
         if (base <= key)
             lo = mid;
         else
@@ -630,7 +676,7 @@ __device__ __forceinline__ void run_task(const Desc &d, int64_t t) {
 template <int R, int RF, int ROT>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles(const Desc d) {
-    run_task<R, RF, ROT>(d, blockIdx.x);
+    run_task<R, RF, ROT>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
 }
 
 // Many problems: every block finds its problem by the task bases.
@@ -638,18 +684,20 @@ template <int R, int RF, int ROT>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles_batch(const Desc *__restrict__ descs, int n_desc) {
     const int64_t t = blockIdx.x;
-    run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, true)], t);
+    run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
 struct FinLds {
     double part[kFinSplit][3][kFinBodies];
-    unsigned long long keys[kRankTile];
+    int scan[kMaxBuckets + 1];
+    int wave_total[kFinalizeThreads / kWave];
 };
 
 // Body block lb of a problem: 32 bodies, each body's slot sum split over 8
-// threads (fixed ranges, combined in a fixed order: deterministic); group
-// label = union-find root.
-__device__ __forceinline__ void finalize_bodies(FinLds &F, const Desc &d, int64_t lb) {
+// threads (fixed ranges, combined in a fixed order: deterministic; field
+// bodies were summed completely by their field task and are only checked),
+// and each body's group label.
+__device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t lb) {
     const int tid = threadIdx.x;
     auto &part = F.part;
     const int col = tid % kFinBodies, split = tid / kFinBodies;
@@ -672,7 +720,7 @@ __device__ __forceinline__ void finalize_bodies(FinLds &F, const Desc &d, int64_
     part[split][1][col] = sy;
     part[split][2][col] = sz;
     __syncthreads();
-    bool root_of_group = false, nonfinite = false;
+    bool nonfinite = false, root_of_group = false;
     if (split == 0 && k < d.n) {
         if (own_sum) {
             for (int s2 = 1; s2 < kFinSplit; ++s2) {
@@ -683,126 +731,162 @@ __device__ __forceinline__ void finalize_bodies(FinLds &F, const Desc &d, int64_
             d.ax[k] = sx;
             d.ay[k] = sy;
             d.az[k] = sz;
-        } else {  // a field body: written by its field task
+        } else {
             sx = d.ax[k];
             sy = d.ay[k];
             sz = d.az[k];
         }
         nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
+        // group label = union-find root, the smallest index of the component
         const int g = uf_find(d.parent, (int)k);
         d.group_id[k] = g;
-        root_of_group = d.touched[k] && g == (int)k;
-        d.touched[k] = 0;
+        const int touched = d.touched[k];
+        root_of_group = touched && g == (int)k;
+        if (touched) d.touched[k] = 0;
     }
     const int groups = __syncthreads_count(root_of_group);
     const int bad = __syncthreads_or(nonfinite);
     if (tid == 0) {
-        if (groups) atomicAdd(d.ctr + 2, (unsigned long long)groups);
-        if (bad) atomicOr(d.ctr + 3, kStatusNonfinite);
-        if (lb == 0) *d.n_pairs_out = (int64_t)d.ctr[0];
+        if (groups) atomicAdd(d.ctr + kCtrGroups, (unsigned long long)groups);
+        if (bad) atomicOr(d.ctr + kCtrStatus, kStatusNonfinite);
     }
 }
 
-// Rank block r (of rank_per_problem) of a problem: canonical position of each
-// stored pair = number of smaller keys (i, j), counted tile by tile.
-__device__ __forceinline__ void finalize_ranks(FinLds &F, const Desc &d, int r, int rank_per_problem) {
-    const int tid = threadIdx.x;
-    unsigned long long *keys = F.keys;
-    const unsigned long long found = d.ctr[0];
-    const int64_t ns = (int64_t)found < d.pair_scratch_cap ? (int64_t)found : d.pair_scratch_cap;
-    const int64_t side = (ns + kRankTile - 1) / kRankTile;
-    for (int64_t t = r; t < side * side; t += rank_per_problem) {
-        const int64_t pc = t / side, kc = t % side;
-        const int64_t kq = kc * kRankTile + tid;
-        __syncthreads();
-        if (kq < ns) {
-            const int2 e = d.pairs[kq];
-            keys[tid] = ((unsigned long long)(unsigned)e.x << 32) | (unsigned)e.y;
-        }
-        __syncthreads();
-        const int64_t me = pc * kRankTile + tid;
-        const int nk = (ns - kc * kRankTile) < kRankTile ? (int)(ns - kc * kRankTile) : kRankTile;
-        if (me < ns) {
-            const int2 e = d.pairs[me];
-            const unsigned long long mine = ((unsigned long long)(unsigned)e.x << 32) | (unsigned)e.y;
-            int less = 0;
-            for (int q = 0; q < nk; ++q) less += keys[q] < mine;
-            if (less) atomicAdd(d.rank + me, less);
-        }
+// Exclusive prefix sums of the problem's bucket counts into F.scan[0..nb]
+// (F.scan[nb] = total), by one block.
+__device__ __forceinline__ void scan_buckets(FinLds &F, const Desc &d) {
+    constexpr int per = (kMaxBuckets + kFinalizeThreads - 1) / kFinalizeThreads;
+    const int tid = threadIdx.x, nb = d.nb;
+    int v[per], run = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int idx = tid * per + k;
+        v[k] = idx < nb ? d.bcnt[idx] : 0;
+        run += v[k];
+    }
+    // inclusive scan of the per-thread totals: within the wave, then across waves
+    int incl = run;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int up = __shfl_up(incl, off);
+        if (lane() >= off) incl += up;
+    }
+    if (lane() == kWave - 1) F.wave_total[wave_id()] = incl;
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave_id(); ++w) base += F.wave_total[w];
+    int excl = base + incl - run;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        const int idx = tid * per + k;
+        if (idx <= nb) F.scan[idx] = excl;
+        excl += v[k];
+    }
+    if (tid == kFinalizeThreads - 1) F.scan[nb] = excl;  // the total (nb may equal kMaxBuckets)
+    __syncthreads();
+}
+
+// Scatter block r of `blocks`: each stored pair to a free slot of its bucket
+// (order inside a bucket is arbitrary here and fixed by the closing kernel).
+// Block 0 also publishes the bucket starts.
+__device__ __forceinline__ void scatter_pairs(FinLds &F, const Desc &d, int r, int blocks) {
+    const int64_t found = (int64_t)d.ctr[kCtrPairs];
+    if (found > d.pair_scratch_cap) return;  // not every pair was stored: no order to produce
+    scan_buckets(F, d);
+    if (r == 0)
+        for (int k = threadIdx.x; k <= d.nb; k += kFinalizeThreads) d.bstart[k] = F.scan[k];
+    for (int64_t p = (int64_t)r * kFinalizeThreads + threadIdx.x; p < found; p += (int64_t)blocks * kFinalizeThreads) {
+        const int2 e = d.pairs[p];
+        const int bk = bucket_of(d, e.x);
+        const int slot = F.scan[bk] + atomicAdd(d.bfill + bk, 1);
+        d.sorted[slot] = e;
     }
 }
 
-__device__ __forceinline__ void scatter_block(const Desc &d) {
-    const int64_t b = blockIdx.x;
+// Block fb of a problem's final kernel: body blocks first, then the pair
+// scatter blocks.
+__device__ __forceinline__ void final_block(FinLds &F, const Desc &d, int64_t fb, int scatter_blocks) {
+    if (fb < d.n_blk)
+        sum_and_label(F, d, fb);
+    else
+        scatter_pairs(F, d, (int)(fb - d.n_blk), scatter_blocks);
+}
+
+// Closing block c of `blocks`, after the final kernel: each pair's canonical
+// position = its bucket's start + the number of smaller keys in its bucket;
+// pairs written out, union-find and bucket scratch returned to zero, scalar
+// outputs (block 0).
+__device__ __forceinline__ void close_block(const Desc &d, int c, int blocks) {
     const int tid = threadIdx.x;
-    const int64_t lb = b - d.blk_base;
-    const int64_t stride = d.n_blk * kFinalizeThreads;
-    const int64_t found = *d.n_pairs_out;
-    const int64_t ns = found < d.pair_scratch_cap ? found : d.pair_scratch_cap;
+    const int64_t found = (int64_t)d.ctr[kCtrPairs];
     const int64_t cap = d.pair_cap < d.pair_scratch_cap ? d.pair_cap : d.pair_scratch_cap;
     const bool fits = found <= cap;
-    for (int64_t p = lb * kFinalizeThreads + tid; p < ns; p += stride) {
-        const int r = d.rank[p];
-        d.rank[p] = 0;
-        if (fits) {
-            const int2 e = d.pairs[p];
-            d.pair_i[r] = e.x;
-            d.pair_j[r] = e.y;
+    const int64_t stride = (int64_t)blocks * kFinalizeThreads;
+    if (found <= d.pair_scratch_cap) {
+        for (int64_t s = (int64_t)c * kFinalizeThreads + tid; s < found; s += stride) {
+            const int2 e = d.sorted[s];
+            const int bk = bucket_of(d, e.x);
+            const int b0 = d.bstart[bk], b1 = d.bstart[bk + 1];
+            const unsigned long long mine = ((unsigned long long)(unsigned)e.x << 32) | (unsigned)e.y;
+            int less = 0;
+            for (int q = b0; q < b1; ++q) {
+                const int2 o = d.sorted[q];
+                less += (((unsigned long long)(unsigned)o.x << 32) | (unsigned)o.y) < mine;
+            }
+            if (fits) {
+                d.pair_i[b0 + less] = e.x;
+                d.pair_j[b0 + less] = e.y;
+            }
+            d.parent[e.x] = 0;  // only bodies of stored pairs can have a parent
+            d.parent[e.y] = 0;
         }
+    } else {  // pairs beyond the scratch list: clear every body
+        for (int64_t k = (int64_t)c * kFinalizeThreads + tid; k < d.n; k += stride) d.parent[k] = 0;
     }
-    for (int64_t k = lb * kFinalizeThreads + tid; k < d.n; k += stride) d.parent[k] = 0;
-    if (lb == 0 && tid == 0) {
-        *d.n_groups_out = (int32_t)d.ctr[2];
-        *d.status_out = (int32_t)(d.ctr[3] | (fits ? 0ull : kStatusCapacity));
-        d.ctr[0] = d.ctr[1] = d.ctr[2] = d.ctr[3] = 0;
+    for (int64_t k = (int64_t)c * kFinalizeThreads + tid; k < d.nb; k += stride) {
+        d.bcnt[k] = 0;
+        d.bfill[k] = 0;
+    }
+    if (c == 0 && tid == 0) {
+        *d.n_pairs_out = found;
+        *d.n_groups_out = (int32_t)d.ctr[kCtrGroups];
+        *d.status_out = (int32_t)(d.ctr[kCtrStatus] | (fits ? 0ull : kStatusCapacity));
+        for (int k = 0; k < kCtrSlots; ++k) d.ctr[k] = 0;
     }
 }
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_finalize(const Desc d, int rank_blocks) {
+__global__ __launch_bounds__(kFinalizeThreads) void k_final(const Desc d, int scatter_blocks) {
     __shared__ FinLds F;
-    const int64_t b = blockIdx.x;
-    if (b < d.n_blk)
-        finalize_bodies(F, d, b);
-    else
-        finalize_ranks(F, d, (int)(b - d.n_blk), rank_blocks);
+    final_block(F, d, blockIdx.x, scatter_blocks);
 }
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_finalize_batch(const Desc *__restrict__ descs,
-                                                                      int n_desc, int64_t n_blk_total,
-                                                                      int rank_per_problem) {
+__global__ __launch_bounds__(kFinalizeThreads) void k_final_batch(const Desc *__restrict__ descs, int n_desc,
+                                                                  int scatter_blocks) {
     __shared__ FinLds F;
-    const int64_t b = blockIdx.x;
-    if (b < n_blk_total) {
-        const Desc &d = descs[problem_of(descs, n_desc, b, false)];
-        finalize_bodies(F, d, b - d.blk_base);
-    } else {
-        const int64_t rb = b - n_blk_total;
-        const int p = (int)(rb / rank_per_problem);
-        if (p < n_desc) finalize_ranks(F, descs[p], (int)(rb % rank_per_problem), rank_per_problem);
-    }
+    const Desc &d = descs[problem_of(descs, n_desc, blockIdx.x, 1)];
+    final_block(F, d, blockIdx.x - d.fin_base, scatter_blocks);
 }
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_scatter(const Desc d) { scatter_block(d); }
+__global__ __launch_bounds__(kFinalizeThreads) void k_close(const Desc d, int blocks) {
+    close_block(d, blockIdx.x, blocks);
+}
 
-__global__ __launch_bounds__(kFinalizeThreads) void k_scatter_batch(const Desc *__restrict__ descs,
-                                                                     int n_desc) {
-    scatter_block(descs[problem_of(descs, n_desc, blockIdx.x, false)]);
+__global__ __launch_bounds__(kFinalizeThreads) void k_close_batch(const Desc *__restrict__ descs, int blocks) {
+    close_block(descs[blockIdx.x / blocks], blockIdx.x % blocks, blocks);
 }
 
 template <int R, int RF, int ROT>
-void launch_tiles(int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc,
-                  hipStream_t stream) {
+void launch_tiles(int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc, hipStream_t stream) {
     if (descs)
-        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0,
-                           stream, descs, n_desc);
+        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream,
+                           descs, n_desc);
     else
-        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream,
-                           one);
+        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream, one);
 }
 
 template <int R>
-void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &one, const Desc *descs,
-                    int n_desc, hipStream_t stream) {
+void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc,
+                    hipStream_t stream) {
     if (rf == 2) {
         if (rot) launch_tiles<R, 2, 1>(n_tasks, one, descs, n_desc, stream);
         else launch_tiles<R, 2, 0>(n_tasks, one, descs, n_desc, stream);
@@ -815,8 +899,8 @@ void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &one, const Des
 }  // namespace
 
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc,
-                       int64_t n_tasks_total, int64_t n_blk_total, const LaunchCfg &cfg,
-                       hipStream_t stream, hipEvent_t *ev) {
+                       int64_t n_tasks_total, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
+                       hipEvent_t *ev) {
     const Desc &inl = descs_host[0];
     const Desc *dd = n_desc == 1 ? nullptr : descs_dev;
     if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return hipErrorUnknown;
@@ -826,27 +910,22 @@ hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc
             case 2: launch_tiles_r<2>(cfg.field_rows, cfg.rotate, n_tasks_total, inl, dd, n_desc, stream); break;
             default: launch_tiles_r<4>(cfg.field_rows, cfg.rotate, n_tasks_total, inl, dd, n_desc, stream); break;
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     }
     if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return hipErrorUnknown;
-    const int64_t rank_blocks = (int64_t)cfg.rank_blocks_per_problem * n_desc;
+    const int sb = cfg.scatter_blocks_per_problem, cb = cfg.close_blocks_per_problem;
     if (dd)
-        hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)(n_blk_total + rank_blocks)),
-                           dim3(kFinalizeThreads), 0, stream, dd, n_desc, n_blk_total,
-                           cfg.rank_blocks_per_problem);
+        hipLaunchKernelGGL(k_final_batch, dim3((unsigned)n_fin_total), dim3(kFinalizeThreads), 0, stream, dd,
+                           n_desc, sb);
     else
-        hipLaunchKernelGGL(k_finalize, dim3((unsigned)(n_blk_total + rank_blocks)), dim3(kFinalizeThreads),
-                           0, stream, inl, cfg.rank_blocks_per_problem);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_final, dim3((unsigned)n_fin_total), dim3(kFinalizeThreads), 0, stream, inl, sb);
+    if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     if (dd)
-        hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)n_blk_total), dim3(kFinalizeThreads), 0, stream,
-                           dd, n_desc);
+        hipLaunchKernelGGL(k_close_batch, dim3((unsigned)(n_desc * cb)), dim3(kFinalizeThreads), 0, stream, dd,
+                           cb);
     else
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)n_blk_total), dim3(kFinalizeThreads), 0, stream, inl);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_close, dim3((unsigned)cb), dim3(kFinalizeThreads), 0, stream, inl, cb);
+    if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     if (ev && hipEventRecord(ev[2], stream) != hipSuccess) return hipErrorUnknown;
     return hipSuccess;
 }

@@ -101,3 +101,13 @@ def test_fold_balances_block_rows(n):
     per_row = np.bincount(tasks[tasks[:, 0] == 0][:, 1], minlength=blocks)
     assert per_row.max() - per_row.min() <= 1
     assert len(tasks) == blocks * (blocks + 1) // 2
+
+
+@pytest.mark.parametrize("n,n_m,rows", [(64 * 9, 64 * 9, 1), (3000, 500, 2), (900, 128, 1), (1, 0, 1)])
+def test_launch_order_puts_field_tasks_first(n, n_m, rows):
+    """Field tasks (the long ones when the massive rows are many) are
+    launched before the triangle's block pairs."""
+    tasks = B.plan_tasks(n, n_m, rows, 1)
+    kinds = tasks[:, 0] if len(tasks) else np.zeros(0)
+    n_field = int((kinds == 1).sum())
+    assert (kinds[:n_field] == 1).all() and (kinds[n_field:] == 0).all()

@@ -214,3 +214,63 @@ def test_batch_matches_plain_and_oracle(ora, rows):
             assert p["acc"].tobytes() == g["acc"].tobytes(), "batched acc differs from the plain call"
         plain_ctx.close()
     ctx.close()
+
+
+def _tight_screen_pairs(n_pairs, seed, dt, vscale):
+    """Head-on pairs for which the screen's reach bound is tight
+    (rc_i = rc_j = |w| dt / 2), the end-of-step separation a few ulp either
+    side of rc, all moving with a common velocity up to `vscale` (the screen's
+    expanded velocity term cancels there)."""
+    rng = np.random.default_rng(seed)
+    xs, vs, rhs = [], [], []
+    for k in range(n_pairs):
+        rh = rng.uniform(0.01, 0.05)
+        c = F * rh
+        u = rng.normal(size=3); u /= np.linalg.norm(u)
+        speed = 2.0 * c / dt
+        s = 1.0 + rng.integers(-8, 9) * 2.0 ** -50
+        d = -(2.0 * c * s + speed * dt) * u
+        common = rng.normal(size=3) * vscale
+        base = rng.uniform(-15, 15, 3)
+        xs += [base, base + d]
+        vs += [common, common + speed * u]
+        rhs += [rh, rh]
+    X, V = np.array(xs), np.array(vs)
+    return dict(x=X[:, 0].copy(), y=X[:, 1].copy(), z=X[:, 2].copy(), vx=V[:, 0].copy(),
+                vy=V[:, 1].copy(), vz=V[:, 2].copy(), m=np.full(len(xs), 1e-9), rh=np.array(rhs))
+
+
+@pytest.mark.parametrize("vscale", [0.0, 0.5, 1e3])
+def test_tight_screen_moving_frame(ctx, ora, vscale):
+    s = _tight_screen_pairs(1200, seed=91, dt=DT, vscale=vscale)
+    n = s["x"].size
+    G.say("tight-screen pairs", n, "common velocity scale", vscale)
+    gpu = G.run_gpu(ctx, s, n - 1, DT, F)
+    ref = ora.kick_encounter(s, n - 1, DT, F)
+    G.check_pairs_groups(gpu, ref)
+    near = sum(1 for i, j in zip(ref["pair_i"], ref["pair_j"]) if j == i + 1 and i % 2 == 0)
+    assert 100 < near < 1100, near
+
+
+def test_batch_crowded_problems(ora):
+    """Crowded problems in a batch: tens of thousands of flagged pairs, so the
+    per-wave candidate queues fill up and are drained inside the tasks, and
+    one encounter group spans almost every body."""
+    import torch
+    from paper_2304_07325_amd import binding as B
+    specs = [(400, 399, 21, 0.3), (500, 50, 22, 4.0), (300, 299, 23, 0.2)]
+    states = [G.dense_state(n, seed=s, box=b, n_m=nm) for (n, nm, s, b) in specs]
+    total = sum(n for n, _, _, _ in specs)
+    refs = [ora.kick_encounter(s, nm, DT, F) for s, (n, nm, _, _) in zip(states, specs)]
+    assert len(refs[0]["pair_i"]) > 20000
+    G.say("batch of crowded problems", [len(r["pair_i"]) for r in refs])
+    ctx = B.Context(max_n=total, max_pairs=1 << 18)
+    dev = [B.to_device_state(s) for s in states]
+    outs = [B.Outputs(n, 1 << 16) for n, _, _, _ in specs]
+    ctx.kick_encounter_batch([(d, nm, DT, F, o) for d, (n, nm, _, _), o in zip(dev, specs, outs)])
+    torch.cuda.synchronize()
+    for (n, nm, _, _), s, o, ref in zip(specs, states, outs, refs):
+        g = o.to_host()
+        G.check_pairs_groups(g, ref)
+        G.check_acc(s, nm, g["acc"], ref["acc"])
+    ctx.close()
