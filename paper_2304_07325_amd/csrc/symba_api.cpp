@@ -271,9 +271,10 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.bstart = c->bstart;
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
-    const symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
+    const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
-    hipError_t e = symba::launch_step(&d, nullptr, 1, d.n_tasks, symba::final_blocks(n, kScatterBlocks), cfg,
+    const symba::TileGroup g{rows, field_rows, 0, 1, 0, d.n_tasks};
+    hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
@@ -281,36 +282,50 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
 int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t n_problems,
                                void *stream) {
     if (!c || !probs || n_problems < 1 || n_problems > c->max_problems) return SYMBA_EINVAL;
-    int64_t total_n = 0, max_tri = 0;
+    int64_t total_n = 0;
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
         if (bad_state(&q.state) || bad_out(&q.out)) return SYMBA_EINVAL;
         if (q.n < 1 || q.n_m < 0 || q.n_m > q.n || bad_scalar(q.dt, q.rcrit_factor)) return SYMBA_EINVAL;
         total_n += q.n;
-        max_tri = std::max<int64_t>(max_tri, q.n_m >= q.n - 1 ? q.n : q.n_m);
     }
     if (total_n > c->max_n) return SYMBA_ETOOBIG;
     if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
-    const int rows = rows_for(max_tri, c->opt_rows);
-    const int field_rows = field_rows_for(0, c->opt_field_rows);
-    std::vector<Desc> ds((size_t)n_problems);
-    std::vector<Plan> plans((size_t)n_problems);
-    size_t partial_total = 0;
-    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0;
-    const symba::LaunchCfg cfg{rows, field_rows, c->opt_rotate, c->opt_screen, kScatterBlocksBatch,
-                               kCloseBlocksBatch};
+    // Each problem gets the tile size a single call would give it, so its
+    // results do not depend on the rest of the batch; problems are ordered by
+    // tile size and each size is one tile-kernel launch.
+    std::vector<int> rows((size_t)n_problems), frows((size_t)n_problems), order((size_t)n_problems);
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
-        plans[k] = make_plan(q.n, q.n_m, rows, field_rows);
-        partial_total += plans[k].partial_doubles;
+        const int64_t n_tri = q.n_m >= q.n - 1 ? q.n : q.n_m;
+        rows[k] = rows_for(n_tri, c->opt_rows);
+        frows[k] = field_rows_for(q.n - n_tri, c->opt_field_rows);
+        order[k] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return rows[a] != rows[b] ? rows[a] < rows[b] : frows[a] < frows[b];
+    });
+    std::vector<Desc> ds((size_t)n_problems);
+    std::vector<Plan> plans((size_t)n_problems);
+    std::vector<symba::TileGroup> groups;
+    size_t partial_total = 0;
+    for (int32_t s = 0; s < n_problems; ++s) {
+        const symba_problem &q = probs[order[s]];
+        plans[s] = make_plan(q.n, q.n_m, rows[order[s]], frows[order[s]]);
+        partial_total += plans[s].partial_doubles;
     }
     int rc = grow_partial(c, partial_total);
     if (rc != SYMBA_OK) return rc;
+    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0;
     size_t partial_off = 0;
-    for (int32_t k = 0; k < n_problems; ++k) {
+    const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
+    for (int32_t s = 0; s < n_problems; ++s) {
+        const int k = order[s];
         const symba_problem &q = probs[k];
-        Desc &d = ds[k];
-        fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[k], field_rows);
+        if (groups.empty() || groups.back().rows != rows[k] || groups.back().field_rows != frows[k])
+            groups.push_back(symba::TileGroup{rows[k], frows[k], s, s, task_total, 0});
+        Desc &d = ds[s];
+        fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[s], frows[k]);
         d.task_base = task_total;
         d.partial = c->partial + partial_off;
         d.parent = c->parent + body_off;
@@ -320,16 +335,18 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.sorted = c->sorted + pair_off;
         d.bcnt = c->bcnt + body_off;
         d.bfill = c->bfill + body_off;
-        d.bstart = c->bstart + body_off + k;
+        d.bstart = c->bstart + body_off + s;
         d.nb = symba::bucket_count(q.n);
         d.pair_scratch_cap = share;
-        d.ctr = c->ctr + symba::kCtrSlots * (int64_t)k;
+        d.ctr = c->ctr + symba::kCtrSlots * (int64_t)s;
         d.fin_base = fin_total;
         task_total += d.n_tasks;
         fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);
         body_off += q.n;
         pair_off += share;
-        partial_off += plans[k].partial_doubles;
+        partial_off += plans[s].partial_doubles;
+        groups.back().p1 = s + 1;
+        groups.back().n_tasks += d.n_tasks;
     }
     hipStream_t st = (hipStream_t)stream;
     const bool same = c->descs_last.size() == ds.size() &&
@@ -344,8 +361,8 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         c->upload_pending = true;
         c->descs_last = ds;
     }
-    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, task_total, fin_total, cfg, st,
-                                      timing_slot(c));
+    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, groups.data(), (int)groups.size(),
+                                      fin_total, cfg, st, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
 

@@ -60,9 +60,16 @@ struct Desc {
     unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
 };
 
-struct LaunchCfg {
+// Problems [p0, p1) of a launch that share a tile size: their tasks are
+// [task_begin, task_begin + n_tasks) of the launch's task numbering.
+struct TileGroup {
     int rows;        // 1, 2 or 4
     int field_rows;  // 1 or 2
+    int p0, p1;
+    int64_t task_begin, n_tasks;
+};
+
+struct LaunchCfg {
     int rotate;      // 0 DPP, 1 ds_bpermute
     int screen;      // 0 FP64 reach screen, 1 FP32 pre-screen
     int scatter_blocks_per_problem;  // pair-scatter blocks per problem (final kernel)
@@ -106,14 +113,14 @@ inline int64_t final_blocks(int64_t n, int scatter_blocks) {
 
 inline int32_t bucket_count(int64_t n) { return (int32_t)(n < kMaxBuckets ? n : kMaxBuckets); }
 
-// Launch the three kernels of one step over n_desc problems: the tile kernel,
-// the final kernel (body sums and labels, pairs into index buckets) and the
-// closing kernel (canonical pair order, outputs, scratch reset).
+// Launch the three kernels of one step over n_desc problems: the tile kernel
+// (once per group of problems sharing a tile size), the final kernel (body
+// sums and labels, pairs into index buckets) and the closing kernel
+// (canonical pair order, outputs, scratch reset).
 // descs_dev is a device copy of descs (may be null when n_desc == 1).  ev,
 // when not null, holds three events recorded before the tile kernel, after
 // it, and after the closing kernel.
-hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc,
-                       int64_t n_tasks_total, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
-                       hipEvent_t *ev);
+hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
+                       int n_groups, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream, hipEvent_t *ev);
 
 }  // namespace symba

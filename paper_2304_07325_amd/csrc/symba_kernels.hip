@@ -679,11 +679,12 @@ void k_tiles(const Desc d) {
     run_task<R, RF, ROT>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
 }
 
-// Many problems: every block finds its problem by the task bases.
+// Many problems of one tile size: every block finds its problem by the task
+// bases (descs is the group's slice of the launch's descriptors).
 template <int R, int RF, int ROT>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
-void k_tiles_batch(const Desc *__restrict__ descs, int n_desc) {
-    const int64_t t = blockIdx.x;
+void k_tiles_batch(const Desc *__restrict__ descs, int n_desc, int64_t task_begin) {
+    const int64_t t = task_begin + blockIdx.x;
     run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
@@ -876,39 +877,39 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_close_batch(const Desc *__
 }
 
 template <int R, int RF, int ROT>
-void launch_tiles(int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc, hipStream_t stream) {
+void launch_tiles(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
     if (descs)
-        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream,
-                           descs, n_desc);
+        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream,
+                           descs + g.p0, g.p1 - g.p0, g.task_begin);
     else
-        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)n_tasks), dim3(kTaskThreads), 0, stream, one);
+        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream, one);
 }
 
 template <int R>
-void launch_tiles_r(int rf, int rot, int64_t n_tasks, const Desc &one, const Desc *descs, int n_desc,
-                    hipStream_t stream) {
-    if (rf == 2) {
-        if (rot) launch_tiles<R, 2, 1>(n_tasks, one, descs, n_desc, stream);
-        else launch_tiles<R, 2, 0>(n_tasks, one, descs, n_desc, stream);
+void launch_tiles_r(const TileGroup &g, int rot, const Desc &one, const Desc *descs, hipStream_t stream) {
+    if (g.field_rows == 2) {
+        if (rot) launch_tiles<R, 2, 1>(g, one, descs, stream);
+        else launch_tiles<R, 2, 0>(g, one, descs, stream);
     } else {
-        if (rot) launch_tiles<R, 1, 1>(n_tasks, one, descs, n_desc, stream);
-        else launch_tiles<R, 1, 0>(n_tasks, one, descs, n_desc, stream);
+        if (rot) launch_tiles<R, 1, 1>(g, one, descs, stream);
+        else launch_tiles<R, 1, 0>(g, one, descs, stream);
     }
 }
 
 }  // namespace
 
-hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc,
-                       int64_t n_tasks_total, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
-                       hipEvent_t *ev) {
+hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
+                       int n_groups, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream, hipEvent_t *ev) {
     const Desc &inl = descs_host[0];
     const Desc *dd = n_desc == 1 ? nullptr : descs_dev;
     if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return hipErrorUnknown;
-    if (n_tasks_total > 0) {
-        switch (cfg.rows) {
-            case 1: launch_tiles_r<1>(cfg.field_rows, cfg.rotate, n_tasks_total, inl, dd, n_desc, stream); break;
-            case 2: launch_tiles_r<2>(cfg.field_rows, cfg.rotate, n_tasks_total, inl, dd, n_desc, stream); break;
-            default: launch_tiles_r<4>(cfg.field_rows, cfg.rotate, n_tasks_total, inl, dd, n_desc, stream); break;
+    for (int k = 0; k < n_groups; ++k) {
+        const TileGroup &g = groups[k];
+        if (g.n_tasks <= 0) continue;
+        switch (g.rows) {
+            case 1: launch_tiles_r<1>(g, cfg.rotate, inl, dd, stream); break;
+            case 2: launch_tiles_r<2>(g, cfg.rotate, inl, dd, stream); break;
+            default: launch_tiles_r<4>(g, cfg.rotate, inl, dd, stream); break;
         }
         if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     }

@@ -206,13 +206,54 @@ def test_batch_matches_plain_and_oracle(ora, rows):
             ref = ora.kick_encounter(s, nm, DT, F)
             G.check_pairs_groups(g, ref)
             G.check_acc(s, nm, g["acc"], ref["acc"])
-    if rows:
-        plain_ctx = B.Context(max_n=max(n for n, _, _ in specs), max_pairs=1 << 16)
-        plain_ctx.set_option(B.OPT_TILE_ROWS, rows)
-        for (n, nm, _), d, g in zip(specs, dev, got):
-            p = G.run_gpu(plain_ctx, {k: v.cpu().numpy() for k, v in d.items()}, nm, DT, F)
-            assert p["acc"].tobytes() == g["acc"].tobytes(), "batched acc differs from the plain call"
-        plain_ctx.close()
+    # every problem gets the tile size a single call gives it, so its results
+    # are bit-identical to the plain call's whatever else is in the batch
+    plain_ctx = B.Context(max_n=max(n for n, _, _ in specs), max_pairs=1 << 16)
+    plain_ctx.set_option(B.OPT_TILE_ROWS, rows)
+    for (n, nm, _), d, g in zip(specs, dev, got):
+        p = G.run_gpu(plain_ctx, {k: v.cpu().numpy() for k, v in d.items()}, nm, DT, F)
+        assert p["acc"].tobytes() == g["acc"].tobytes(), "batched acc differs from the plain call"
+    plain_ctx.close()
+    ctx.close()
+
+
+def test_batch_graph_replays_match_eager(ora):
+    """A batched step captured in a HIP graph: every replay, with eager calls
+    in between, gives the eager call's outputs bit for bit."""
+    import torch
+    from paper_2304_07325_amd import binding as B
+    specs = [(900, 899, 31), (1500, 150, 32), (4100, 4099, 33), (300, 299, 34)]
+    states = [G.dense_state(n, seed=s, box=4.0, n_m=nm) for (n, nm, s) in specs]
+    total = sum(n for n, _, _ in specs)
+    G.say("graph replay of a batch", specs)
+    ctx = B.Context(max_n=total, max_pairs=1 << 18)
+    dev = [B.to_device_state(s) for s in states]
+    outs = [B.Outputs(n, 1 << 15) for n, _, _ in specs]
+    probs = [(d, nm, DT, F, o) for d, (n, nm, _), o in zip(dev, specs, outs)]
+    ctx.kick_encounter_batch(probs)
+    torch.cuda.synchronize()
+    eager = [o.to_host() for o in outs]
+    for (n, nm, _), s, e in zip(specs, states, eager):
+        G.check_pairs_groups(e, ora.kick_encounter(s, nm, DT, F))
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        ctx.kick_encounter_batch(probs, stream=stream)
+    for rep in range(3):
+        for o in outs:
+            o.acc.zero_()
+            o.group_id.fill_(-1)
+        graph.replay()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, outs):
+            g = o.to_host()
+            assert g["acc"].tobytes() == e["acc"].tobytes(), f"replay {rep}: acc differs"
+            assert np.array_equal(g["pair_i"], e["pair_i"]) and np.array_equal(g["pair_j"], e["pair_j"])
+            assert np.array_equal(g["group_id"], e["group_id"]) and g["n_groups"] == e["n_groups"]
+            assert g["status"] == e["status"]
+        ctx.kick_encounter_batch(probs)   # eager work between replays
+        torch.cuda.synchronize()
     ctx.close()
 
 
@@ -274,3 +315,25 @@ def test_batch_crowded_problems(ora):
         G.check_pairs_groups(g, ref)
         G.check_acc(s, nm, g["acc"], ref["acc"])
     ctx.close()
+
+
+def test_hot50k_full_size(ctx, ora):
+    """The 50k-body hot disk at full size, as the library runs it: the pair
+    list compared entry by entry with the oracle's (every one of the 1.25e9
+    pairs tested), the groups with the oracle's connected components of that
+    list, and the accelerations of 600 sampled bodies (the oracle sums each
+    one over all massive bodies)."""
+    w = dg.WORKLOADS["hot50k"]
+    d = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"])
+    s = d.state(3)
+    n, n_m = w["n"], w["n_massive"]
+    G.say("hot50k full size")
+    gpu = G.run_gpu(ctx, s, n_m, DT, F, pair_cap=1 << 20)
+    pi, pj = ora.pairs(s, n_m, DT, F)
+    gid, ng = ora.groups(n, pi, pj)
+    G.check_pairs_groups(gpu, dict(pair_i=pi, pair_j=pj, group_id=gid, n_groups=ng))
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, 1, n_m - 1, n - 1], pi[:50], rng.choice(n, 546, replace=False)]))
+    ref = np.stack([ora.accel_body(s, n_m, int(k)) for k in idx])
+    err, lim = G.check_acc(s, n_m, gpu["acc"][idx], ref, bodies=idx)
+    print(f"hot50k: pairs {len(pi)}, groups {ng}, sampled max rel err {err:.2e}, limited {lim}")
