@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--workload", default="disk10k")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-warmup", type=int, default=1000)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -171,6 +175,9 @@ def main():
     batched = None
     if not args.no_batch:
         batched = bench_batch(args, B, dg, torch)
+    served = None
+    if not args.no_serve:
+        served = bench_serve(args, dg, torch)
 
     result = {
         "metric": "FP64 pair-interactions/s (10k disk) + p50/p99 step latency, batched vs plain",
@@ -193,12 +200,42 @@ def main():
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic_from_profiles(),
                      "kernel": "k_tiles", "kernel_us": tile_ms * 1e3, "flop_per_launch": flop},
         "batched": batched,
+        "served": served,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(disk, n_m, dt, f)
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def bench_serve(args, dg, torch):
+    """256 resident simulations (N log-uniform in [500, 50000], all massive,
+    even ids cold and odd ids hot), step requests arriving as a Poisson stream
+    that names a uniformly random simulation, served by continuous batching:
+    latency from arrival to completion (host monotonic clock).  Run with a
+    200 GB device budget (nothing is evicted) and again with 0.5 GB, which
+    keeps only part of the population resident."""
+    from paper_2304_07325_amd.serve import Server
+    dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
+    pop = dg.serving_population()
+    sims = [(dg.make_disk(n, nm, kind, seed).state(0), nm) for (n, nm, kind, seed) in pop]
+    total = sum(n for n, _, _, _ in pop)
+    res = {"simulations": len(sims), "bodies": total, "rate_hz": args.serve_rate}
+    runs = (("budget_200GB", 200 << 30, None, args.serve_requests, args.serve_warmup),
+            ("budget_0.5GB", 512 << 20, 100_000, args.serve_requests // 5, args.serve_warmup // 5))
+    for name, budget, max_bodies, n_req, warm in runs:
+        t, ids = dg.poisson_arrivals(args.serve_rate, n_req + warm, len(sims))
+        srv = Server(sims, budget, dt, f, max_batch_bodies=max_bodies)
+        srv.preload(reserve=max(srv._need(k) - srv.sims[k].resident_bytes for k in range(len(sims))))
+        torch.cuda.synchronize()
+        stats = srv.serve(t, ids, warmup=warm)
+        srv.close()
+        res[name] = stats
+        log(f"serve {name}: p50 {stats['latency_ms']['p50']:.3f} ms p99 {stats['latency_ms']['p99']:.3f} ms, "
+            f"{stats['steps_per_s']:.0f} steps/s, mean batch {stats['mean_batch']:.1f}, "
+            f"uploads {stats['uploads']}, evictions {stats['evictions']}")
+    return res
 
 
 def bench_batch(args, B, dg, torch):

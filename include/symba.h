@@ -164,6 +164,15 @@ const char *symba_strerror(int code);
 int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,
                          int64_t *tasks, int64_t cap);
 
+/* Host-only helper (no device work): device scratch, in bytes, that one
+ * problem of n bodies (n_m massive) with an output pair capacity of
+ * pair_cap takes from the context in a call with the context's current
+ * options: the per-task partial sums (which grow the context's buffer on
+ * demand) plus the per-body and per-pair scratch.  Lets a caller that keeps
+ * many problems resident budget device memory before it batches them.
+ * Returns -1 on invalid arguments. */
+int64_t symba_scratch_bytes(const symba_ctx *ctx, int64_t n, int64_t n_m, int64_t pair_cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -40,7 +40,8 @@ class symba_problem(ctypes.Structure):
 
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
-           "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing")
+           "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
+           "symba_scratch_bytes")
 
 
 class SymbaError(RuntimeError):
@@ -67,6 +68,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.symba_strerror.argtypes = [ctypes.c_int]
     lib.symba_read_timing.restype = ctypes.c_int
     lib.symba_read_timing.argtypes = [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]
+    lib.symba_scratch_bytes.restype = _I64
+    lib.symba_scratch_bytes.argtypes = [_P, _I64, _I64, _I64]
     lib.symba_plan_tasks.restype = _I64
     lib.symba_plan_tasks.argtypes = [_I64, _I64, ctypes.c_int32, ctypes.c_int32, _P, _I64]
     return lib
@@ -174,6 +177,13 @@ class Context:
         _check(lib().symba_read_timing(self._h, ctypes.byref(t), ctypes.byref(fz), ctypes.byref(n)),
                "symba_read_timing")
         return t.value, fz.value, n.value
+
+    def scratch_bytes(self, n: int, n_m: int, pair_cap: int) -> int:
+        """symba_scratch_bytes: device scratch one problem takes in a call."""
+        v = lib().symba_scratch_bytes(self._h, int(n), int(n_m), int(pair_cap))
+        if v < 0:
+            raise SymbaError("symba_scratch_bytes: invalid arguments")
+        return int(v)
 
     def kick_encounter(self, state: dict, n_m: int, dt: float, rcrit_factor: float,
                        out: Outputs | None = None, stream=None) -> Outputs:

@@ -409,4 +409,14 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
     return total;
 }
 
+int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t pair_cap) {
+    if (!c || n < 1 || n_m < 0 || n_m > n || pair_cap < 0) return -1;
+    const int64_t n_tri = n_m >= n - 1 ? n : n_m;
+    const Plan p = make_plan(n, n_m, rows_for(n_tri, c->opt_rows), field_rows_for(n - n_tri, c->opt_field_rows));
+    const int64_t per_body = 4 * (int64_t)sizeof(int32_t) + (int64_t)sizeof(int32_t);  // parent, touched, buckets
+    const int64_t per_pair = 2 * (int64_t)sizeof(int2);                                 // pair lists
+    return (int64_t)(p.partial_doubles * sizeof(double)) + per_body * n + per_pair * pair_cap +
+           (int64_t)sizeof(Desc);
+}
+
 }  // extern "C"
