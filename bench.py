@@ -256,6 +256,14 @@ def bench_batch(args, B, dg, torch):
     cap = sum(o.pair_cap for o in outs)
     ctx = B.Context(max_n=total_n, max_pairs=cap)
     probs = [(st, nm, dt, f, o) for st, (n, nm, _), o in zip(states, specs, outs)]
+    # autotune: one representative problem per size class (power of two of n_tri)
+    tuned = {}
+    for st, (n, nm, _), o in zip(states, specs, outs):
+        n_tri = n if nm >= n - 1 else nm
+        cls = n_tri.bit_length() - 1
+        if cls not in tuned:
+            tuned[cls] = ctx.autotune(st, nm, dt, f, out=o)
+    log("autotuned bodies per lane by size class 2^k: " + ", ".join(f"{k}:{v}" for k, v in sorted(tuned.items())))
     rounds = args.batch_rounds
 
     def plain_round():
@@ -265,7 +273,8 @@ def bench_batch(args, B, dg, torch):
     def batch_round():
         ctx.kick_encounter_batch(probs)
 
-    res = {"disks": len(specs), "bodies": total_n, "pairs_per_round": total_pairs}
+    res = {"disks": len(specs), "bodies": total_n, "pairs_per_round": total_pairs,
+           "autotuned_rows": {f"2^{k}": v for k, v in sorted(tuned.items())}}
     for name, fn in (("plain", plain_round), ("batched", batch_round)):
         for _ in range(3):
             fn()

@@ -164,6 +164,19 @@ const char *symba_strerror(int code);
 int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,
                          int64_t *tasks, int64_t cap);
 
+/* Tile-size autotuner: runs the problem (arguments as symba_kick_encounter)
+ * with every tile size (64, 128 and 256 massive bodies per block row), times
+ * the calls with HIP events, and keeps the fastest size in the context for
+ * every later problem of the same size class (the same power of two of
+ * n_tri = N if N_m >= N - 1, else N_m), in single and batched calls alike,
+ * unless SYMBA_OPT_TILE_ROWS forces a size.  Results stay within the same
+ * tolerance whichever size runs (pairs and groups are exact); accelerations
+ * are bit-reproducible for a given size.  Writes the outputs of a final call
+ * with the chosen size, *chosen_rows (may be NULL) = bodies per lane (1, 2 or
+ * 4).  Synchronizes the stream; do not call it under graph capture. */
+int symba_autotune(symba_ctx *ctx, const symba_state *s, int64_t n, int64_t n_m, double dt,
+                   double rcrit_factor, const symba_out *out, void *stream, int32_t *chosen_rows);
+
 /* Host-only helper (no device work): device scratch, in bytes, that one
  * problem of n bodies (n_m massive) with an output pair capacity of
  * pair_cap takes from the context in a call with the context's current

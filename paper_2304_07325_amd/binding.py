@@ -41,7 +41,7 @@ class symba_problem(ctypes.Structure):
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
-           "symba_scratch_bytes")
+           "symba_scratch_bytes", "symba_autotune")
 
 
 class SymbaError(RuntimeError):
@@ -68,6 +68,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.symba_strerror.argtypes = [ctypes.c_int]
     lib.symba_read_timing.restype = ctypes.c_int
     lib.symba_read_timing.argtypes = [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]
+    lib.symba_autotune.restype = ctypes.c_int
+    lib.symba_autotune.argtypes = [_P, ctypes.POINTER(symba_state), _I64, _I64, _D, _D,
+                                   ctypes.POINTER(symba_out), _P, ctypes.POINTER(ctypes.c_int32)]
     lib.symba_scratch_bytes.restype = _I64
     lib.symba_scratch_bytes.argtypes = [_P, _I64, _I64, _I64]
     lib.symba_plan_tasks.restype = _I64
@@ -197,6 +200,21 @@ class Context:
                                         float(rcrit_factor), ctypes.byref(o), _stream_handle(stream))
         _check(rc, "symba_kick_encounter")
         return out
+
+    def autotune(self, state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs | None = None,
+                 stream=None) -> int:
+        """symba_autotune: times every tile size on this problem, keeps the
+        fastest for its size class; returns the chosen bodies per lane."""
+        n = int(state["x"].numel())
+        if out is None:
+            out = Outputs(n, min(self.max_pairs, max(4 * n, 4096)), device=state["x"].device)
+        st = _state_struct(state)
+        o = out.c_struct()
+        rows = ctypes.c_int32(0)
+        rc = lib().symba_autotune(self._h, ctypes.byref(st), n, int(n_m), float(dt), float(rcrit_factor),
+                                  ctypes.byref(o), _stream_handle(stream), ctypes.byref(rows))
+        _check(rc, "symba_autotune")
+        return int(rows.value)
 
     def kick_encounter_batch(self, problems, stream=None):
         """problems: list of (state, n_m, dt, rcrit_factor, Outputs)."""

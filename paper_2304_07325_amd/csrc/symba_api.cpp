@@ -35,6 +35,8 @@ struct symba_ctx {
     bool upload_pending = false;
     // options
     int opt_rows = 0, opt_field_rows = 0, opt_rotate = 0, opt_screen = 0, opt_timing = 0;
+    // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
+    int tuned_rows[64] = {};
     // timing events (SYMBA_OPT_TIMING): three per timed call
     std::vector<hipEvent_t> events;
     size_t timed_calls = 0;
@@ -65,9 +67,17 @@ hipEvent_t *timing_slot(symba_ctx *c) {
 
 // Bodies per lane of the triangle tiles: R = 1 keeps small problems spread
 // over many workgroups; larger R amortises the lane rotation and shrinks the
-// partial-sum buffer (B x 3 x N doubles, B = N / (64 R)).
-int rows_for(int64_t n_tri, int opt) {
-    if (opt) return opt;
+// partial-sum buffer (B x 3 x N doubles, B = N / (64 R)).  A forced option
+// wins, then a size class tuned by symba_autotune, then the built-in table.
+int size_class(int64_t n_tri) {
+    int c = 0;
+    while (c < 63 && (int64_t(2) << c) <= n_tri) ++c;
+    return c;
+}
+
+int rows_for(const symba_ctx *c, int64_t n_tri) {
+    if (c->opt_rows) return c->opt_rows;
+    if (n_tri > 0 && c->tuned_rows[size_class(n_tri)]) return c->tuned_rows[size_class(n_tri)];
     if (n_tri >= 30000) return 4;
     if (n_tri >= 4000) return 2;
     return 1;
@@ -252,7 +262,7 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     if (n > c->max_n) return SYMBA_ETOOBIG;
     if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
     const int n_tri_guess = (int)(n_m >= n - 1 ? n : n_m);
-    const int rows = rows_for(n_tri_guess, c->opt_rows);
+    const int rows = rows_for(c, n_tri_guess);
     const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
     const Plan p = make_plan(n, n_m, rows, field_rows);
     int rc = grow_partial(c, p.partial_doubles);
@@ -298,7 +308,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
         const int64_t n_tri = q.n_m >= q.n - 1 ? q.n : q.n_m;
-        rows[k] = rows_for(n_tri, c->opt_rows);
+        rows[k] = rows_for(c, n_tri);
         frows[k] = field_rows_for(q.n - n_tri, c->opt_field_rows);
         order[k] = k;
     }
@@ -409,10 +419,63 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
     return total;
 }
 
+int symba_autotune(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt, double rcrit_factor,
+                   const symba_out *out, void *stream, int32_t *chosen_rows) {
+    if (!c || bad_state(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || bad_scalar(dt, rcrit_factor)) return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    const int64_t n_tri = n_m >= n - 1 ? n : n_m;
+    if (std::min(n_m, n - 1) < 1) {  // no pairs: nothing to tune
+        if (chosen_rows) *chosen_rows = rows_for(c, n_tri);
+        return symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SYMBA_EDEVICE;
+    }
+    const int saved_rows = c->opt_rows, saved_timing = c->opt_timing;
+    c->opt_timing = 0;
+    constexpr int kRows[3] = {1, 2, 4};
+    constexpr int kReps = 3;
+    int best = 0, rc = SYMBA_OK;
+    float best_ms = 0.f;
+    for (int r : kRows) {
+        c->opt_rows = r;
+        rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);  // warm-up (and buffer growth)
+        if (rc != SYMBA_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = SYMBA_EDEVICE; break; }
+        for (int k = 0; k < kReps && rc == SYMBA_OK; ++k)
+            rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
+        if (rc != SYMBA_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = SYMBA_EDEVICE;
+            break;
+        }
+        if (best == 0 || ms < best_ms) {
+            best = r;
+            best_ms = ms;
+        }
+    }
+    c->opt_rows = saved_rows;
+    c->opt_timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SYMBA_OK) return rc;
+    c->tuned_rows[size_class(n_tri)] = best;
+    if (chosen_rows) *chosen_rows = best;
+    // leave the problem's outputs as a call with the tuned size writes them
+    return symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
+}
+
 int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t pair_cap) {
     if (!c || n < 1 || n_m < 0 || n_m > n || pair_cap < 0) return -1;
     const int64_t n_tri = n_m >= n - 1 ? n : n_m;
-    const Plan p = make_plan(n, n_m, rows_for(n_tri, c->opt_rows), field_rows_for(n - n_tri, c->opt_field_rows));
+    const Plan p = make_plan(n, n_m, rows_for(c, n_tri), field_rows_for(n - n_tri, c->opt_field_rows));
     const int64_t per_body = 4 * (int64_t)sizeof(int32_t) + (int64_t)sizeof(int32_t);  // parent, touched, buckets
     const int64_t per_pair = 2 * (int64_t)sizeof(int2);                                 // pair lists
     return (int64_t)(p.partial_doubles * sizeof(double)) + per_body * n + per_pair * pair_cap +

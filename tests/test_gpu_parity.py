@@ -337,3 +337,28 @@ def test_hot50k_full_size(ctx, ora):
     ref = np.stack([ora.accel_body(s, n_m, int(k)) for k in idx])
     err, lim = G.check_acc(s, n_m, gpu["acc"][idx], ref, bodies=idx)
     print(f"hot50k: pairs {len(pi)}, groups {ng}, sampled max rel err {err:.2e}, limited {lim}")
+
+
+def test_autotune_chooses_a_size_and_stays_exact(ora):
+    """The autotuner times every tile size, keeps one for the size class, and
+    the outputs of its final call and of a later call of the same size are
+    bit-identical and match the oracle."""
+    from paper_2304_07325_amd import binding as B
+    s = G.dense_state(3000, seed=61, box=6.0)
+    G.say("autotune n=3000")
+    ctx = B.Context(max_n=4096, max_pairs=1 << 16)
+    dev = B.to_device_state(s)
+    out = B.Outputs(3000, 1 << 15)
+    rows = ctx.autotune(dev, 2999, DT, F, out=out)
+    assert rows in (1, 2, 4)
+    tuned = out.to_host()
+    ref = ora.kick_encounter(s, 2999, DT, F)
+    G.check_pairs_groups(tuned, ref)
+    G.check_acc(s, 2999, tuned["acc"], ref["acc"])
+    again = G.run_gpu(ctx, s, 2999, DT, F, pair_cap=1 << 15)
+    assert again["acc"].tobytes() == tuned["acc"].tobytes()
+    forced = B.Context(max_n=4096, max_pairs=1 << 16)
+    forced.set_option(B.OPT_TILE_ROWS, rows)
+    assert G.run_gpu(forced, s, 2999, DT, F, pair_cap=1 << 15)["acc"].tobytes() == tuned["acc"].tobytes()
+    forced.close()
+    ctx.close()
