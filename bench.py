@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--workload", default="disk10k")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-others", action="store_true", help="skip the 1k, 100k-field and 50k-hot disks")
+    ap.add_argument("--no-hot-check", action="store_true",
+                    help="skip the oracle check of one 50k hot-disk evaluation (about 20 s of host time)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -178,6 +181,9 @@ def main():
     served = None
     if not args.no_serve:
         served = bench_serve(args, dg, torch)
+    others = None
+    if not args.no_others:
+        others = bench_other_workloads(args, B, dg, torch)
 
     result = {
         "metric": "FP64 pair-interactions/s (10k disk) + p50/p99 step latency, batched vs plain",
@@ -201,12 +207,82 @@ def main():
                      "kernel": "k_tiles", "kernel_us": tile_ms * 1e3, "flop_per_launch": flop},
         "batched": batched,
         "served": served,
+        "other_workloads": others,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(disk, n_m, dt, f)
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def bench_other_workloads(args, B, dg, torch):
+    """The 1k disk, the 100k-body field disk (1000 massive) and the 50k-body
+    hot disk: throughput over their Kepler-advanced states, and for the hot
+    disk the screen's candidates vs confirmed pairs and one evaluation checked
+    against the oracle (every pair and label, 600 sampled accelerations)."""
+    import numpy as np
+    res = {}
+    dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
+    for name in ("disk1k", "field100k", "hot50k"):
+        w = dg.WORKLOADS[name]
+        n, n_m, evals = w["n"], w["n_massive"], w["evals"]
+        disk = dg.make_disk(n, n_m, w["kind"], w["seed"])
+        host = [disk.state(k) for k in range(evals)]
+        states = [B.to_device_state(h) for h in host]
+        ctx = B.Context(max_n=n, max_pairs=max(16 * n, 1 << 16))
+        out = B.Outputs(n, max(16 * n, 1 << 16))
+        for k in range(min(3, evals)):
+            ctx.kick_encounter(states[k], n_m, dt, f, out=out)
+        torch.cuda.synchronize()
+        ctx.read_stats()
+        ctx.set_option(B.OPT_TIMING, 1)
+        ctx.read_timing()
+        steps = max(evals, 20)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ctx.kick_encounter(states[k % evals], n_m, dt, f, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        tiles_ms, fin_ms, calls = ctx.read_timing()
+        ctx.set_option(B.OPT_TIMING, 0)
+        cands, flagged, probs = ctx.read_stats()
+        pairs = dg.pair_count(n, n_m)
+        r = dict(n=n, n_m=n_m, kind=w["kind"], steps=steps, pairs_per_step=pairs,
+                 pairs_per_s=pairs * steps / el, ms_per_step=1e3 * el / steps,
+                 tile_kernel_us=1e3 * tiles_ms / max(calls, 1), post_kernels_us=1e3 * fin_ms / max(calls, 1),
+                 screen=dict(candidates_per_step=cands / max(probs, 1), flagged_per_step=flagged / max(probs, 1),
+                             pass_rate=cands / max(probs, 1) / pairs,
+                             confirmed_fraction=flagged / cands if cands else None))
+        if name == "hot50k" and not args.no_hot_check:
+            import oracle
+            ora = oracle.default()
+            k = 3
+            ctx.kick_encounter(states[k], n_m, dt, f, out=out)
+            torch.cuda.synchronize()
+            g = out.to_host()
+            pi, pj = ora.pairs(host[k], n_m, dt, f)
+            gid, ng = ora.groups(n, pi, pj)
+            same_len = len(pi) == len(g["pair_i"])
+            mism = int(len(pi) != len(g["pair_i"])) if not same_len else int(
+                np.count_nonzero((pi != g["pair_i"]) | (pj != g["pair_j"])))
+            missed = len(set(zip(pi.tolist(), pj.tolist())) - set(zip(g["pair_i"].tolist(), g["pair_j"].tolist())))
+            rng = np.random.default_rng(5)
+            idx = rng.choice(n, 600, replace=False)
+            ref = np.stack([ora.accel_body(host[k], n_m, int(b)) for b in idx])
+            rel = np.linalg.norm(g["acc"][idx] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+            r["oracle_check"] = dict(state=k, pairs=len(pi), pair_mismatches=mism, false_negatives=missed,
+                                     label_mismatches=int(np.count_nonzero(gid != g["group_id"])),
+                                     groups=ng, groups_gpu=g["n_groups"],
+                                     acc_rel_err=dict(sampled=len(idx), max=float(rel.max()),
+                                                      p99=float(np.percentile(rel, 99)),
+                                                      median=float(np.median(rel))))
+        ctx.close()
+        res[name] = r
+        log(f"{name}: {r['pairs_per_s']:.3e} pairs/s, {r['ms_per_step']:.3f} ms/step, "
+            f"screen pass rate {r['screen']['pass_rate']:.2e}" +
+            (f", oracle check {r['oracle_check']}" if "oracle_check" in r else ""))
+    return res
 
 
 def bench_serve(args, dg, torch):

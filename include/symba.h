@@ -164,6 +164,14 @@ const char *symba_strerror(int code);
 int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,
                          int64_t *tasks, int64_t cap);
 
+/* Screen statistics accumulated over the context's calls since the last
+ * read: pairs the conservative screen passed to the exact encounter test,
+ * pairs the test flagged (the false-positive rate of the screen is
+ * 1 - flagged/candidates; it has no false negatives by construction) and
+ * problems evaluated.  Waits for the device, then starts a new accumulation.
+ * Any output pointer may be NULL. */
+int symba_read_stats(symba_ctx *ctx, int64_t *candidates, int64_t *flagged, int64_t *problems);
+
 /* Tile-size autotuner: runs the problem (arguments as symba_kick_encounter)
  * with every tile size (64, 128 and 256 massive bodies per block row), times
  * the calls with HIP events, and keeps the fastest size in the context for

@@ -41,7 +41,7 @@ class symba_problem(ctypes.Structure):
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
-           "symba_scratch_bytes", "symba_autotune")
+           "symba_scratch_bytes", "symba_autotune", "symba_read_stats")
 
 
 class SymbaError(RuntimeError):
@@ -68,6 +68,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.symba_strerror.argtypes = [ctypes.c_int]
     lib.symba_read_timing.restype = ctypes.c_int
     lib.symba_read_timing.argtypes = [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]
+    lib.symba_read_stats.restype = ctypes.c_int
+    lib.symba_read_stats.argtypes = [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]
     lib.symba_autotune.restype = ctypes.c_int
     lib.symba_autotune.argtypes = [_P, ctypes.POINTER(symba_state), _I64, _I64, _D, _D,
                                    ctypes.POINTER(symba_out), _P, ctypes.POINTER(ctypes.c_int32)]
@@ -180,6 +182,13 @@ class Context:
         _check(lib().symba_read_timing(self._h, ctypes.byref(t), ctypes.byref(fz), ctypes.byref(n)),
                "symba_read_timing")
         return t.value, fz.value, n.value
+
+    def read_stats(self):
+        """symba_read_stats: (screen candidates, flagged pairs, problems) since the last read."""
+        a, b, c = _I64(), _I64(), _I64()
+        _check(lib().symba_read_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "symba_read_stats")
+        return a.value, b.value, c.value
 
     def scratch_bytes(self, n: int, n_m: int, pair_cap: int) -> int:
         """symba_scratch_bytes: device scratch one problem takes in a call."""

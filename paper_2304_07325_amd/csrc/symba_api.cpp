@@ -26,6 +26,7 @@ struct symba_ctx {
     int32_t *bfill = nullptr;    // [max_n]
     int32_t *bstart = nullptr;   // [max_n + max_problems]
     unsigned long long *ctr = nullptr;  // [kCtrSlots * max_problems]
+    unsigned long long *stats = nullptr;  // [kStatSlots]
     double *partial = nullptr;
     size_t partial_bytes = 0;
     Desc *descs_dev = nullptr;   // [max_problems]
@@ -187,6 +188,7 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->bfill, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->bstart, sizeof(int32_t) * (max_n + kMaxProblems)) == hipSuccess &&
               hipMalloc(&c->ctr, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
+              hipMalloc(&c->stats, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
               hipMalloc(&c->descs_dev, sizeof(Desc) * kMaxProblems) == hipSuccess &&
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
@@ -196,6 +198,7 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
              hipMemset(c->bcnt, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->bfill, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->ctr, 0, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
+             hipMemset(c->stats, 0, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {
@@ -218,6 +221,7 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->bfill);
     (void)hipFree(c->bstart);
     (void)hipFree(c->ctr);
+    (void)hipFree(c->stats);
     (void)hipFree(c->partial);
     (void)hipFree(c->descs_dev);
     if (c->descs_pinned) (void)hipHostFree(c->descs_pinned);
@@ -281,6 +285,7 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.bstart = c->bstart;
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
+    d.stats = c->stats;
     const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
     const symba::TileGroup g{rows, field_rows, 0, 1, 0, d.n_tasks};
@@ -349,6 +354,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.nb = symba::bucket_count(q.n);
         d.pair_scratch_cap = share;
         d.ctr = c->ctr + symba::kCtrSlots * (int64_t)s;
+        d.stats = c->stats;
         d.fin_base = fin_total;
         task_total += d.n_tasks;
         fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);
@@ -417,6 +423,20 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
         }
     }
     return total;
+}
+
+int symba_read_stats(symba_ctx *c, int64_t *candidates, int64_t *flagged, int64_t *problems) {
+    if (!c) return SYMBA_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    unsigned long long h[symba::kStatSlots] = {};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(h, c->stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(c->stats, 0, sizeof h) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return SYMBA_EDEVICE;
+    if (candidates) *candidates = (int64_t)h[symba::kStatCandidates];
+    if (flagged) *flagged = (int64_t)h[symba::kStatFlagged];
+    if (problems) *problems = (int64_t)h[symba::kStatCalls];
+    return SYMBA_OK;
 }
 
 int symba_autotune(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt, double rcrit_factor,

@@ -19,6 +19,12 @@ constexpr int kCtrGroups = 2;  // encounter groups (components with >= 2 bodies)
 constexpr int kCtrStatus = 3;  // status bits
 constexpr int kCtrSlots = 4;
 
+// Context-wide statistics accumulated over calls (read by symba_read_stats).
+constexpr int kStatCandidates = 0;  // pairs passed by the screen to the exact test
+constexpr int kStatFlagged = 1;     // pairs flagged by the exact test
+constexpr int kStatCalls = 2;       // problems evaluated
+constexpr int kStatSlots = 4;
+
 // Per-problem view handed to the kernels: inputs, outputs, plan and scratch slices.
 struct Desc {
     // inputs (device, length n)
@@ -58,6 +64,7 @@ struct Desc {
     int32_t *bstart;      // [nb + 1] bucket starts in the canonical order
     int32_t nb;           // buckets: min(n, kMaxBuckets)
     unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
+    unsigned long long *stats;  // [kStatSlots] context-wide statistics
 };
 
 // Problems [p0, p1) of a launch that share a tile size: their tasks are

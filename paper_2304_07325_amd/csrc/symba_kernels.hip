@@ -245,6 +245,7 @@ __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i,
 
 // Exact test of up to 64 queued candidates, one per lane.
 __device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
+    if (lane() == 0) atomicAdd(d.stats + kStatCandidates, (unsigned long long)count);
     const bool mine = lane() < count;
     uint2 c = make_uint2(0u, 0u);
     if (mine) c = Q.q[(head + lane()) & Q.mask];
@@ -849,6 +850,8 @@ __device__ __forceinline__ void close_block(const Desc &d, int c, int blocks) {
         d.bfill[k] = 0;
     }
     if (c == 0 && tid == 0) {
+        atomicAdd(d.stats + kStatFlagged, (unsigned long long)found);
+        atomicAdd(d.stats + kStatCalls, 1ull);
         *d.n_pairs_out = found;
         *d.n_groups_out = (int32_t)d.ctr[kCtrGroups];
         *d.status_out = (int32_t)(d.ctr[kCtrStatus] | (fits ? 0ull : kStatusCapacity));

@@ -362,3 +362,18 @@ def test_autotune_chooses_a_size_and_stays_exact(ora):
     assert G.run_gpu(forced, s, 2999, DT, F, pair_cap=1 << 15)["acc"].tobytes() == tuned["acc"].tobytes()
     forced.close()
     ctx.close()
+
+
+def test_screen_statistics(ctx):
+    """symba_read_stats: the screen passes at least every flagged pair, and the
+    counts cover the problems evaluated since the last read."""
+    w = dg.WORKLOADS["disk1k"]
+    s = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"]).state(4)
+    G.say("screen statistics disk1k")
+    ctx.read_stats()
+    res = [G.run_gpu(ctx, s, w["n_massive"], DT, F) for _ in range(3)]
+    cands, flagged, probs = ctx.read_stats()
+    assert probs == 3
+    assert flagged == 3 * res[0]["n_pairs"]
+    assert cands >= flagged
+    assert ctx.read_stats() == (0, 0, 0)
