@@ -65,6 +65,7 @@ extern "C" {
 #define SYMBA_OPT_ROTATE 3      /* lane rotation of the j-side sums: 0 = DPP, 1 = ds_bpermute */
 #define SYMBA_OPT_SCREEN 4      /* 0 = FP64 reach screen, 1 = FP32 closest-approach pre-screen */
 #define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
+#define SYMBA_OPT_BIN 6         /* spatial binning: 0 = by problem size, 1 = never, 2 = always */
 
 typedef struct symba_ctx symba_ctx;
 

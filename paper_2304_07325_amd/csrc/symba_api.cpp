@@ -27,6 +27,12 @@ struct symba_ctx {
     int32_t *bstart = nullptr;   // [max_n + max_problems]
     unsigned long long *ctr = nullptr;  // [kCtrSlots * max_problems]
     unsigned long long *stats = nullptr;  // [kStatSlots]
+    int32_t *bin_key = nullptr, *bin_tmp = nullptr, *bin_idx = nullptr;  // [max_n] each
+    double *binned = nullptr;    // [8 * max_n]
+    double *tbox = nullptr;      // [max_boxes * kBoxDoubles]
+    int64_t max_boxes = 0;
+    unsigned long long *bin_bbox = nullptr;  // [12], zero between calls
+    int32_t *bin_temp = nullptr;             // [kBinTempInts]: cell counts and fills (zero between calls), starts
     double *partial = nullptr;
     size_t partial_bytes = 0;
     Desc *descs_dev = nullptr;   // [max_problems]
@@ -35,7 +41,7 @@ struct symba_ctx {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     // options
-    int opt_rows = 0, opt_field_rows = 0, opt_rotate = 0, opt_screen = 0, opt_timing = 0;
+    int opt_rows = 0, opt_field_rows = 0, opt_rotate = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0;
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
     // timing events (SYMBA_OPT_TIMING): three per timed call
@@ -110,6 +116,51 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
     return p;
 }
 
+// Problems with at least this many massive bodies are binned by default (the
+// screen-free tiles then repay the two binning launches).
+constexpr int64_t kBinMinTri = 20000;
+
+bool use_bin(const symba_ctx *c, int64_t n, int64_t n_m) {
+    const int64_t n_tri = n_m >= n - 1 ? n : n_m;
+    if (std::min(n_m, n - 1) < 1 || c->opt_bin == 1) return false;
+    return c->opt_bin == 2 || n_tri >= kBinMinTri;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Points the descriptor's tile-kernel inputs at the binned copies (scratch at
+// body offset body_off, tile boxes at box_off) or at the caller's inputs.
+// Returns 1 when the problem is binned.  The binning temporaries are shared:
+// the problems of a call are binned one after the other.
+int wire_binning(const symba_ctx *c, Desc &d, bool bin, int64_t body_off, int64_t box_off) {
+    d.bx = d.x; d.by = d.y; d.bz = d.z; d.bm = d.m; d.bvx = d.vx; d.bvy = d.vy; d.bvz = d.vz; d.brh = d.rh;
+    d.bidx = nullptr;
+    d.tbox = nullptr;
+    d.bin_key = d.bin_tmp = d.bin_idx = nullptr;
+    d.binned = d.tbox_w = nullptr;
+    d.bin_bbox = nullptr;
+    d.bin_hist = d.bin_fill = d.bin_start = nullptr;
+    d.n_tboxes = d.n_boxes = 0;
+    if (!bin) return 0;
+    const int64_t n = d.n;
+    d.bin_key = c->bin_key + body_off;
+    d.bin_tmp = c->bin_tmp + body_off;
+    d.bin_idx = c->bin_idx + body_off;
+    d.binned = c->binned + 8 * body_off;
+    d.tbox_w = c->tbox + symba::kBoxDoubles * box_off;
+    d.bx = d.binned; d.by = d.binned + n; d.bz = d.binned + 2 * n; d.bm = d.binned + 3 * n;
+    d.bvx = d.binned + 4 * n; d.bvy = d.binned + 5 * n; d.bvz = d.binned + 6 * n; d.brh = d.binned + 7 * n;
+    d.bidx = d.bin_idx;
+    d.tbox = d.tbox_w;
+    d.n_tboxes = ceil_div(d.n_tri, symba::kWave);
+    d.n_boxes = d.n_tboxes + ceil_div(n - d.n_tri, symba::kWave);
+    d.bin_bbox = c->bin_bbox;
+    d.bin_hist = c->bin_temp;
+    d.bin_fill = c->bin_temp + 2 * 2048;
+    d.bin_start = c->bin_temp + 4 * 2048;
+    return 1;
+}
+
 bool bad_scalar(double dt, double f) { return !(dt >= 0.0) || !std::isfinite(dt) || !(f > 0.0) || !std::isfinite(f); }
 
 bool bad_state(const symba_state *s) {
@@ -180,6 +231,7 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
     c->max_n = max_n;
     c->max_pairs = max_pairs;
     c->max_problems = kMaxProblems;
+    c->max_boxes = max_n / symba::kWave + 2 * (int64_t)kMaxProblems;
     bool ok = hipMalloc(&c->parent, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
@@ -189,6 +241,13 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->bstart, sizeof(int32_t) * (max_n + kMaxProblems)) == hipSuccess &&
               hipMalloc(&c->ctr, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
               hipMalloc(&c->stats, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
+              hipMalloc(&c->bin_key, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->bin_tmp, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->bin_idx, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->binned, sizeof(double) * 8 * max_n) == hipSuccess &&
+              hipMalloc(&c->tbox, sizeof(double) * symba::kBoxDoubles * c->max_boxes) == hipSuccess &&
+              hipMalloc(&c->bin_bbox, sizeof(unsigned long long) * 12) == hipSuccess &&
+              hipMalloc(&c->bin_temp, sizeof(int32_t) * symba::kBinTempInts) == hipSuccess &&
               hipMalloc(&c->descs_dev, sizeof(Desc) * kMaxProblems) == hipSuccess &&
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
@@ -196,6 +255,8 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
         ok = hipMemset(c->parent, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->bcnt, 0, sizeof(int32_t) * max_n) == hipSuccess &&
+             hipMemset(c->bin_bbox, 0, sizeof(unsigned long long) * 12) == hipSuccess &&
+             hipMemset(c->bin_temp, 0, sizeof(int32_t) * symba::kBinTempInts) == hipSuccess &&
              hipMemset(c->bfill, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->ctr, 0, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
              hipMemset(c->stats, 0, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
@@ -222,6 +283,13 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->bstart);
     (void)hipFree(c->ctr);
     (void)hipFree(c->stats);
+    (void)hipFree(c->bin_key);
+    (void)hipFree(c->bin_tmp);
+    (void)hipFree(c->bin_idx);
+    (void)hipFree(c->binned);
+    (void)hipFree(c->tbox);
+    (void)hipFree(c->bin_bbox);
+    (void)hipFree(c->bin_temp);
     (void)hipFree(c->partial);
     (void)hipFree(c->descs_dev);
     if (c->descs_pinned) (void)hipHostFree(c->descs_pinned);
@@ -245,6 +313,10 @@ int symba_set_option(symba_ctx *c, int option, int value) {
         case SYMBA_OPT_ROTATE:
             if (value != 0 && value != 1) return SYMBA_EINVAL;
             c->opt_rotate = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_BIN:
+            if (value < 0 || value > 2) return SYMBA_EINVAL;
+            c->opt_bin = value;
             return SYMBA_OK;
         case SYMBA_OPT_TIMING:
             if (value != 0 && value != 1) return SYMBA_EINVAL;
@@ -288,8 +360,9 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.stats = c->stats;
     const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
+    const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
     const symba::TileGroup g{rows, field_rows, 0, 1, 0, d.n_tasks};
-    hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, symba::final_blocks(n, kScatterBlocks), cfg,
+    hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, binned, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
@@ -331,7 +404,8 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     }
     int rc = grow_partial(c, partial_total);
     if (rc != SYMBA_OK) return rc;
-    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0;
+    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0, box_off = 0;
+    int n_binned = 0;
     size_t partial_off = 0;
     const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
     for (int32_t s = 0; s < n_problems; ++s) {
@@ -356,6 +430,8 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.ctr = c->ctr + symba::kCtrSlots * (int64_t)s;
         d.stats = c->stats;
         d.fin_base = fin_total;
+        n_binned += wire_binning(c, d, use_bin(c, q.n, q.n_m), body_off, box_off);
+        box_off += d.n_boxes;
         task_total += d.n_tasks;
         fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);
         body_off += q.n;
@@ -378,7 +454,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         c->descs_last = ds;
     }
     hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, groups.data(), (int)groups.size(),
-                                      fin_total, cfg, st, timing_slot(c));
+                                      n_binned, fin_total, cfg, st, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
 
@@ -496,7 +572,10 @@ int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t 
     if (!c || n < 1 || n_m < 0 || n_m > n || pair_cap < 0) return -1;
     const int64_t n_tri = n_m >= n - 1 ? n : n_m;
     const Plan p = make_plan(n, n_m, rows_for(c, n_tri), field_rows_for(n - n_tri, c->opt_field_rows));
-    const int64_t per_body = 4 * (int64_t)sizeof(int32_t) + (int64_t)sizeof(int32_t);  // parent, touched, buckets
+    const int64_t per_body = 5 * (int64_t)sizeof(int32_t) +                                 // parent, touched, buckets
+                             (use_bin(c, n, n_m) ? 3 * (int64_t)sizeof(int32_t) + 8 * (int64_t)sizeof(double) +
+                                                       symba::kBoxDoubles * (int64_t)sizeof(double) / symba::kWave
+                                                 : 0);  // binning
     const int64_t per_pair = 2 * (int64_t)sizeof(int2);                                 // pair lists
     return (int64_t)(p.partial_doubles * sizeof(double)) + per_body * n + per_pair * pair_cap +
            (int64_t)sizeof(Desc);

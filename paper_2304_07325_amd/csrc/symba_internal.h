@@ -11,6 +11,9 @@ constexpr int kFinalizeThreads = 256;
 constexpr int kFinBodies = 32;     // bodies per finalize block
 constexpr int kFinSplit = kFinalizeThreads / kFinBodies;  // threads per body in the slot sums
 constexpr int kMaxBuckets = 4096;  // index buckets of the canonical pair order
+constexpr int kBoxDoubles = 16;    // tile box record: pos lo[3] hi[3], vel lo[3] hi[3], qmax, pad
+constexpr int kGatherWaves = 4;    // tiles per block of the tile-box kernel
+constexpr int kBinTempInts = 2 * 2048 + 2 * 2048 + 2 * 2049;  // cell counts, fills, starts
 
 // Per-problem device counters (zero between calls).
 constexpr int kCtrPairs = 0;   // flagged pairs found
@@ -29,6 +32,11 @@ constexpr int kStatSlots = 4;
 struct Desc {
     // inputs (device, length n)
     const double *x, *y, *z, *vx, *vy, *vz, *m, *rh;
+    // the same inputs as the tile kernel reads them: the binned copies when
+    // the problem is binned (positions in the binned order), else the inputs
+    const double *bx, *by, *bz, *bvx, *bvy, *bvz, *bm, *brh;
+    const int32_t *bidx;  // [n] caller's index of each binned position, null when not binned
+    const double *tbox;   // [n_boxes][kBoxDoubles] tile boxes, null when not binned
     // caller outputs (device)
     double *ax, *ay, *az;
     int32_t *pair_i, *pair_j;
@@ -51,6 +59,8 @@ struct Desc {
     int64_t task_base;    // first global task of this problem
     int64_t n_blk;        // body blocks of this problem's final kernel (kFinBodies bodies each)
     int64_t fin_base;     // first global final-kernel block of this problem
+    int64_t n_tboxes;     // 64-body tiles of the massive segment [0, n_tri)
+    int64_t n_boxes;      // all tiles (massive, then field [n_tri, n))
     int64_t field_block;  // field bodies per field task (64*field_rows)
     // scratch slices (context-owned)
     double *partial;      // [B][3][n_tri] per-slot partial sums
@@ -65,6 +75,16 @@ struct Desc {
     int32_t nb;           // buckets: min(n, kMaxBuckets)
     unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
     unsigned long long *stats;  // [kStatSlots] context-wide statistics
+    // binning scratch (written by the binning kernels); null when not binned
+    int32_t *bin_key;     // [n] grid cell of each body
+    int32_t *bin_tmp;     // [n] bodies grouped by cell
+    int32_t *bin_idx;     // [n] binned order (the array bidx points at)
+    double *binned;       // [8][n] inputs in the binned order (bx.. point into it)
+    double *tbox_w;       // [n_boxes][kBoxDoubles] (the array tbox points at)
+    unsigned long long *bin_bbox;  // [2][6] segment boxes (atomic max of ordered keys), zero between calls
+    int32_t *bin_hist;    // [2][2048] bodies per cell, zero between calls
+    int32_t *bin_fill;    // [2][2048] cell fill counters, zero between calls
+    int32_t *bin_start;   // [2][2049] cell starts
 };
 
 // Problems [p0, p1) of a launch that share a tile size: their tasks are
@@ -120,14 +140,16 @@ inline int64_t final_blocks(int64_t n, int scatter_blocks) {
 
 inline int32_t bucket_count(int64_t n) { return (int32_t)(n < kMaxBuckets ? n : kMaxBuckets); }
 
-// Launch the three kernels of one step over n_desc problems: the tile kernel
-// (once per group of problems sharing a tile size), the final kernel (body
+// Launch the kernels of one step over n_desc problems: binning (n_binned
+// problems use it), the tile kernel (once per group of
+// problems sharing a tile size), the final kernel (body
 // sums and labels, pairs into index buckets) and the closing kernel
 // (canonical pair order, outputs, scratch reset).
 // descs_dev is a device copy of descs (may be null when n_desc == 1).  ev,
 // when not null, holds three events recorded before the tile kernel, after
 // it, and after the closing kernel.
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
-                       int n_groups, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream, hipEvent_t *ev);
+                       int n_groups, int n_binned, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
+                       hipEvent_t *ev);
 
 }  // namespace symba

@@ -243,12 +243,19 @@ __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i,
     }
 }
 
-// Exact test of up to 64 queued candidates, one per lane.
+// Exact test of up to 64 queued candidates, one per lane (queued as binned
+// positions, tested and reported by the caller's indices).
 __device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
     if (lane() == 0) atomicAdd(d.stats + kStatCandidates, (unsigned long long)count);
     const bool mine = lane() < count;
     uint2 c = make_uint2(0u, 0u);
-    if (mine) c = Q.q[(head + lane()) & Q.mask];
+    if (mine) {
+        c = Q.q[(head + lane()) & Q.mask];
+        // binned -> caller's order (a padding position, possible only next to a
+        // non-finite body, stays out of range and is rejected by the test)
+        if (d.bidx && c.x < (unsigned)d.n && c.y < (unsigned)d.n)
+            c = make_uint2((unsigned)d.bidx[c.x], (unsigned)d.bidx[c.y]);
+    }
     test_and_group(d, mine, (int)c.x, (int)c.y);
 }
 
@@ -288,7 +295,8 @@ __device__ __forceinline__ void drain_rest(const Desc &d, Queue &Q) {
     }
 }
 
-// One body as the tile kernel uses it.  An LDS-side body carries its velocity
+// One body as the tile kernel uses it (read at its position in the binned
+// order, see k_bin).  An LDS-side body carries its velocity
 // in (vx, vy, vz), a register-side body the screen's u = -2 D v; Q is the
 // screen's Q = (1 + 2^-40) (4 (1 + 2^-20) (f rh)^2 + D |v|^2).
 struct Body {
@@ -299,12 +307,12 @@ template <bool REG>
 __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
     Body b;
     if (k < limit) {
-        b.x = d.x[k];
-        b.y = d.y[k];
-        b.z = d.z[k];
-        b.m = d.m[k];
-        const double vx = d.vx[k], vy = d.vy[k], vz = d.vz[k];
-        const double rc = d.f * d.rh[k];
+        b.x = d.bx[k];
+        b.y = d.by[k];
+        b.z = d.bz[k];
+        b.m = d.bm[k];
+        const double vx = d.bvx[k], vy = d.bvy[k], vz = d.bvz[k];
+        const double rc = d.f * d.brh[k];
         const double D = d.screen_dt2;
         const double v2 = __builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx));
         b.Q = kScreenInflate * __builtin_fma(D, v2, kScreenQ * (rc * rc));
@@ -339,6 +347,44 @@ __device__ __forceinline__ Body tile_body(const TaskLds<RS> &L, int q, int idx) 
     const double2 a = L.tile.xy[q][idx], b = L.tile.zm[q][idx], c = L.tile.vxy[q][idx],
                   e = L.tile.vzq[q][idx];
     return Body{a.x, a.y, b.x, b.y, c.x, c.y, e.x, e.y};
+}
+
+// Position and mass of a tile entry (the screen-free loops read nothing else).
+template <int RS>
+__device__ __forceinline__ Body tile_pos(const TaskLds<RS> &L, int q, int idx) {
+    const double2 a = L.tile.xy[q][idx], b = L.tile.zm[q][idx];
+    return Body{a.x, a.y, b.x, b.y, 0.0, 0.0, 0.0, 0.0};
+}
+
+// Box record of massive tile t (64 bodies from position 64 t) and of field
+// tile g (64 bodies from position n_tri + 64 g); -1 for a tile past the end.
+__device__ __forceinline__ int64_t tri_box(const Desc &d, int64_t t) { return t < d.n_tboxes ? t : -1; }
+__device__ __forceinline__ int64_t field_box(const Desc &d, int64_t g) {
+    return d.n_tboxes + g < d.n_boxes ? d.n_tboxes + g : -1;
+}
+
+// Tile boxes of the binned order: no pair between tile a and tile b (indices
+// into the box records) can pass the screen, so none can be flagged.  Over
+// any i in a and j in b, |x_j - x_i| is at least the gap between the
+// position boxes, |v_j - v_i|^2 is at most the sum of the squared widest
+// velocity differences, and q_i, q_j at most the tiles' largest q; the pair
+// screen passes only if r2 < q_i + q_j + D |v_j - v_i|^2, so a gap with
+//   gap^2 (1 - 2^-30) >= (qmax_a + qmax_b + D wmax^2) (1 + 2^-30)
+// (the factors cover the rounding of these few operations) rules out every
+// pair.  A tile with a non-finite value has qmax = NaN and is never ruled out.
+__device__ __forceinline__ bool tiles_apart(const Desc &d, int64_t a, int64_t b) {
+    if (a < 0 || b < 0) return true;  // a tile of padding only: massless and far away
+    const double *A = d.tbox + a * kBoxDoubles, *Bq = d.tbox + b * kBoxDoubles;
+    double gap2 = 0.0, w2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double g = fmax(0.0, fmax(Bq[k] - A[3 + k], A[k] - Bq[3 + k]));
+        gap2 = __builtin_fma(g, g, gap2);
+        const double w = fmax(Bq[9 + k] - A[6 + k], A[9 + k] - Bq[6 + k]);
+        w2 = __builtin_fma(w, w, w2);
+    }
+    const double thr = __builtin_fma(w2, d.screen_dt2, A[12] + Bq[12]);
+    return gap2 * (1.0 - 0x1p-30) >= thr * (1.0 + 0x1p-30);
 }
 
 __device__ __forceinline__ double rotate_dpp(double v) {
@@ -398,7 +444,7 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
 // tile entry (l + t0) mod 64 and ends with those of entry (l + t0 + 16) mod 64.
 // Steps whose screen passed anywhere in the wave are only marked in a scalar
 // bit mask; the candidates are pushed afterwards (no branch in the loop).
-template <int R, int RS, int NACT, int ROT>
+template <int R, int RS, int NACT, int ROT, bool SCR>
 __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> &L, int q, Slots<R> &S,
                                                int64_t ib, int64_t js, int t0, Queue &Q, double &ajx,
                                                double &ajy, double &ajz) {
@@ -406,11 +452,12 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
     const int baddr = ((l + 1) & (kWave - 1)) << 2;
     ajx = ajy = ajz = 0.0;
     unsigned pending = 0;
-    Body Jn = tile_body(L, q, l + t0);
+    Body Jn = SCR ? tile_body(L, q, l + t0) : tile_pos(L, q, l + t0);
 #pragma unroll kRotUnroll
     for (int u = 0; u < kSteps; ++u) {
         const Body J = Jn;
-        Jn = tile_body(L, q, l + t0 + u + 1);  // one step ahead: the LDS latency hides behind this step
+        // one step ahead: the LDS latency hides behind this step
+        Jn = SCR ? tile_body(L, q, l + t0 + u + 1) : tile_pos(L, q, l + t0 + u + 1);
         unsigned long long any = 0;
 #pragma unroll
         for (int r = 0; r < NACT; ++r) {
@@ -425,10 +472,10 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
             ajx = __builtin_fma(-fj, dx, ajx);
             ajy = __builtin_fma(-fj, dy, ajy);
             ajz = __builtin_fma(-fj, dz, ajz);
-            any |= __builtin_amdgcn_ballot_w64(
-                screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q));
+            if (SCR)
+                any |= __builtin_amdgcn_ballot_w64(screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q));
         }
-        pending |= nonzero(any) << u;
+        if (SCR) pending |= nonzero(any) << u;
         if (ROT == 0) {
             ajx = rotate_dpp(ajx);
             ajy = rotate_dpp(ajy);
@@ -488,8 +535,8 @@ __device__ __forceinline__ void diagonal_tiles(const Desc &d, const TaskLds<RS> 
                                                int t0, Queue &Q, double (&aj)[R][3]) {
     if constexpr (QS < R) {
         if constexpr (QS > 0)
-            rotation_range<R, RS, QS, ROT>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0], aj[QS][1],
-                                           aj[QS][2]);
+            rotation_range<R, RS, QS, ROT, true>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0],
+                                                 aj[QS][1], aj[QS][2]);
         else
             aj[0][0] = aj[0][1] = aj[0][2] = 0.0;
         diagonal_range<R, RS, QS>(d, L, S, ib, t0, Q);
@@ -512,14 +559,33 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
         S.b[r] = load_body<true>(d, ib + r * kWave + l, d.n_tri);
         S.ax[r] = S.ay[r] = S.az[r] = 0.0;
     }
+    // lane r R + q decides stationary tile r against streamed tile q (the box
+    // loads overlap the body loads); bit q of free_q: screen-free tile q
+    unsigned free_q = 0;
+    if (d.tbox != nullptr && I != J) {
+        const bool apart = l >= R * R || tiles_apart(d, tri_box(d, I * R + l / R), tri_box(d, J * R + l % R));
+        const unsigned long long m = __ballot(apart);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            bool all = true;
+#pragma unroll
+            for (int r = 0; r < R; ++r) all = all && ((m >> (r * R + q)) & 1ull);
+            free_q |= (all ? 1u : 0u) << q;
+        }
+    }
     stage(d, L, jb, R, d.n_tri);
     __syncthreads();
     double aj[R][3];
     if (I != J) {
 #pragma unroll
-        for (int q = 0; q < R; ++q)
-            rotation_range<R, RS, R, ROT>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
-                                          aj[q][2]);
+        for (int q = 0; q < R; ++q) {
+            if ((free_q >> q) & 1u)
+                rotation_range<R, RS, R, ROT, false>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0],
+                                                     aj[q][1], aj[q][2]);
+            else
+                rotation_range<R, RS, R, ROT, true>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0],
+                                                    aj[q][1], aj[q][2]);
+        }
     } else {
         diagonal_tiles<R, RS, ROT, 0>(d, L, S, ib, t0, Q, aj);
     }
@@ -558,6 +624,37 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     drain_rest(d, Q);
 }
 
+// This wave's 16 rows [t0, t0 + 16) of staged massive tile q against the
+// lane's field bodies (one-sided pairs); returns the bit mask of the steps
+// whose screen passed somewhere in the wave.
+template <int RF, int RS, bool SCR>
+__device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS> &L, int q, int64_t s0, int t0,
+                                                const Body (&fbody)[RF], double (&ax)[RF], double (&ay)[RF],
+                                                double (&az)[RF]) {
+    unsigned pending = 0;
+    for (int u = 0; u < kSteps; ++u) {
+        const int64_t row = s0 + q * kWave + t0 + u;
+        if (row >= d.n_rows) break;
+        // the same massive body in every lane
+        const Body I = SCR ? tile_body(L, q, t0 + u) : tile_pos(L, q, t0 + u);
+        unsigned long long any = 0;
+#pragma unroll
+        for (int r = 0; r < RF; ++r) {
+            const Body &Fb = fbody[r];
+            const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double fj = I.m * inv_r3(r2, d.k15, d.k1875);
+            ax[r] = __builtin_fma(-fj, dx, ax[r]);
+            ay[r] = __builtin_fma(-fj, dy, ay[r]);
+            az[r] = __builtin_fma(-fj, dz, az[r]);
+            if (SCR)
+                any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q));
+        }
+        if (SCR) pending |= nonzero(any) << u;
+    }
+    return pending;
+}
+
 // Field block fb against every massive row, by the four waves of the
 // workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
 // pairs; the field accelerations are complete at the end and written directly.
@@ -576,28 +673,25 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
     for (int64_t s0 = 0; s0 < d.n_rows; s0 += RS * kWave) {
         const int64_t left = d.n_rows - s0;
         const int nq = left >= RS * kWave ? RS : (int)((left + kWave - 1) / kWave);
+        // lane q RF + r decides field tile r against massive tile q of the chunk
+        unsigned free_q = 0;
+        if (d.tbox != nullptr) {
+            const bool apart = l >= nq * RF ||
+                               tiles_apart(d, field_box(d, fb * RF + l % RF), tri_box(d, s0 / kWave + l / RF));
+            const unsigned long long m = __ballot(apart);
+            for (int q = 0; q < nq; ++q) {
+                bool all = true;
+#pragma unroll
+                for (int r = 0; r < RF; ++r) all = all && ((m >> (q * RF + r)) & 1ull);
+                free_q |= (all ? 1u : 0u) << q;
+            }
+        }
         stage(d, L, s0, nq, d.n_rows);
         __syncthreads();
         for (int q = 0; q < nq; ++q) {
-            unsigned pending = 0;
-            for (int u = 0; u < kSteps; ++u) {
-                const int64_t row = s0 + q * kWave + t0 + u;
-                if (row >= d.n_rows) break;
-                const Body I = tile_body(L, q, t0 + u);  // the same massive body in every lane
-                unsigned long long any = 0;
-#pragma unroll
-                for (int r = 0; r < RF; ++r) {
-                    const Body &Fb = fbody[r];
-                    const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
-                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const double fj = I.m * inv_r3(r2, d.k15, d.k1875);
-                    ax[r] = __builtin_fma(-fj, dx, ax[r]);
-                    ay[r] = __builtin_fma(-fj, dy, ay[r]);
-                    az[r] = __builtin_fma(-fj, dz, az[r]);
-                    any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q));
-                }
-                pending |= nonzero(any) << u;
-            }
+            const bool apart = (free_q >> q) & 1u;
+            unsigned pending = apart ? field_range<RF, RS, false>(d, L, q, s0, t0, fbody, ax, ay, az)
+                                     : field_range<RF, RS, true>(d, L, q, s0, t0, fbody, ax, ay, az);
             while (pending) {
                 const int u = __builtin_ctz(pending);
                 pending &= pending - 1;
@@ -626,8 +720,9 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
     __syncthreads();
     for (int e = threadIdx.x; e < RF * kWave; e += kTaskThreads) {
         const int r = e / kWave, ll = e % kWave;
-        const int64_t k = f0 + e;
-        if (k >= d.n) continue;
+        const int64_t pos = f0 + e;
+        if (pos >= d.n) continue;
+        const int64_t k = d.bidx ? d.bidx[pos] : pos;
         double sum[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -689,6 +784,323 @@ void k_tiles_batch(const Desc *__restrict__ descs, int n_desc, int64_t task_begi
     run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
+// ---------------------------------------------------------------------------
+// Binning: bodies of each segment (massive [0, n_tri), field [n_tri, n)) are
+// put in a spatial order so that the 64-body tiles are compact and most tile
+// pairs are provably too far apart for any encounter (tiles_apart), which
+// lets the tile kernel skip the screen for them.  The order only changes how
+// the work is grouped: it is a deterministic function of the input (cell of a
+// Morton-ordered grid over the segment's bounding box, ties by index), so
+// results stay reproducible.  Six small kernels: bounding box, cell counts,
+// cell starts, cell fill, order within cells (with the copy of the inputs in
+// the binned order), tile boxes.
+
+constexpr int kBinBlock = 256;          // threads of the per-body binning kernels
+constexpr int kBinPerThread = 2;        // bodies per thread (their loads in flight together)
+constexpr int kBinChunk = kBinBlock * kBinPerThread;
+constexpr int kBinCellBits = 11;
+constexpr int kBinCells = 1 << kBinCellBits;
+constexpr int kBinScanThreads = 1024;
+
+// Order-preserving map of a double to an unsigned integer (for atomic min/max).
+__device__ __forceinline__ unsigned long long ord_key(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ord_value(unsigned long long u) {
+    const unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double((long long)b);
+}
+
+struct Grid {
+    double lo[3], scale[3];
+    int bits[3];
+};
+
+// The segment's grid: cells of the bounding box, with the bits given one at
+// a time to the axis whose cells are longest (flat, empty or non-finite axes
+// get none).  bbox holds max(~key(min)) and max(key(max)) per axis.
+__device__ __forceinline__ Grid make_grid(const unsigned long long *bbox) {
+    Grid g;
+    double ext[3];
+    for (int a = 0; a < 3; ++a) {
+        const double mn = ord_value(~bbox[a]), mx = ord_value(bbox[3 + a]);
+        ext[a] = mx - mn;
+        if (!(ext[a] > 0.0) || !isfinite(ext[a])) ext[a] = 0.0;
+        g.lo[a] = isfinite(mn) ? mn : 0.0;
+        g.bits[a] = 0;
+    }
+    for (int b = 0; b < kBinCellBits; ++b) {
+        int best = -1;
+        double len = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double l = ext[a] / (double)(1 << g.bits[a]);
+            if (l > len) {
+                len = l;
+                best = a;
+            }
+        }
+        if (best < 0) break;
+        ++g.bits[best];
+    }
+    for (int a = 0; a < 3; ++a) g.scale[a] = g.bits[a] ? (double)(1 << g.bits[a]) / ext[a] : 0.0;
+    return g;
+}
+
+// Grid cell of a position: each coordinate quantized to its axis' bits (NaN
+// and out-of-range values clamp into the grid), the bits interleaved from the
+// most significant level down (Morton order).
+__device__ __forceinline__ int grid_cell(const Grid &g, double x, double y, double z) {
+    const double c[3] = {x, y, z};
+    int q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double top = (double)((1 << g.bits[a]) - 1);
+        q[a] = (int)fmin(fmax((c[a] - g.lo[a]) * g.scale[a], 0.0), top);
+    }
+    int cell = 0;
+#pragma unroll
+    for (int lev = kBinCellBits - 1; lev >= 0; --lev)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (g.bits[a] > lev) cell = (cell << 1) | ((q[a] >> lev) & 1);
+    return cell;
+}
+
+__device__ __forceinline__ int segment_of(const Desc &d, int64_t k) { return k < d.n_tri ? 0 : 1; }
+
+// Bounding box of each segment: block-level min/max, then one atomic per
+// value and segment.
+__global__ __launch_bounds__(kBinBlock) void k_bin_bbox(const Desc d) {
+    __shared__ double red[2][6][kBinBlock / kWave];
+    double r[2][6];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r[s][a] = INFINITY;
+            r[s][3 + a] = -INFINITY;
+        }
+    const int64_t k0 = (int64_t)blockIdx.x * kBinChunk + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+        const int64_t k = k0 + (int64_t)u * kBinBlock;
+        if (k < d.n) {
+            const double c[3] = {d.x[k], d.y[k], d.z[k]};
+            const int s = segment_of(d, k);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {  // fmin/fmax drop NaN
+                r[s][a] = fmin(r[s][a], c[a]);
+                r[s][3 + a] = fmax(r[s][3 + a], c[a]);
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            double v = r[s][a];
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                const double o = __shfl_xor(v, off);
+                v = a < 3 ? fmin(v, o) : fmax(v, o);
+            }
+            if (lane() == 0) red[s][a][wave_id()] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < 12) {
+        const int s = threadIdx.x / 6, a = threadIdx.x % 6;
+        double v = red[s][a][0];
+        for (int w = 1; w < kBinBlock / kWave; ++w) v = a < 3 ? fmin(v, red[s][a][w]) : fmax(v, red[s][a][w]);
+        if (isfinite(v)) atomicMax(d.bin_bbox + 6 * s + a, a < 3 ? ~ord_key(v) : ord_key(v));
+    }
+}
+
+// Cell of every body, counted per segment and cell.
+__global__ __launch_bounds__(kBinBlock) void k_bin_count(const Desc d) {
+    const Grid g0 = make_grid(d.bin_bbox), g1 = make_grid(d.bin_bbox + 6);
+    const int64_t k0 = (int64_t)blockIdx.x * kBinChunk + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+        const int64_t k = k0 + (int64_t)u * kBinBlock;
+        if (k < d.n) {
+            const int s = segment_of(d, k);
+            const int cell = grid_cell(s ? g1 : g0, d.x[k], d.y[k], d.z[k]);
+            d.bin_key[k] = cell;
+            atomicAdd(d.bin_hist + s * kBinCells + cell, 1);
+        }
+    }
+}
+
+// Start of every cell (exclusive prefix sums of the counts, per segment, by
+// one block); the counts, fill counters and boxes return to zero.
+__global__ __launch_bounds__(kBinScanThreads) void k_bin_scan(const Desc d) {
+    __shared__ int wave_total[kBinScanThreads / kWave];
+    constexpr int per = kBinCells / kBinScanThreads;
+    const int tid = threadIdx.x;
+    for (int s = 0; s < 2; ++s) {
+        int v[per], run = 0;
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            v[k] = d.bin_hist[s * kBinCells + tid * per + k];
+            run += v[k];
+        }
+        int incl = run;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int up = __shfl_up(incl, off);
+            if (lane() >= off) incl += up;
+        }
+        if (lane() == kWave - 1) wave_total[wave_id()] = incl;
+        __syncthreads();
+        int excl = incl - run;
+        for (int w = 0; w < wave_id(); ++w) excl += wave_total[w];
+        int32_t *start = d.bin_start + s * (kBinCells + 1);
+#pragma unroll
+        for (int k = 0; k < per; ++k) {
+            start[tid * per + k] = excl;
+            excl += v[k];
+            d.bin_hist[s * kBinCells + tid * per + k] = 0;
+            d.bin_fill[s * kBinCells + tid * per + k] = 0;
+        }
+        if (tid == kBinScanThreads - 1) start[kBinCells] = excl;
+        __syncthreads();  // wave_total is reused by the next segment
+    }
+    if (tid < 12) d.bin_bbox[tid] = 0;
+}
+
+// Every body into a free slot of its cell (any order within the cell).
+__global__ __launch_bounds__(kBinBlock) void k_bin_scatter(const Desc d) {
+    const int64_t k0 = (int64_t)blockIdx.x * kBinChunk + threadIdx.x;
+    int cells[kBinPerThread];
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+        const int64_t k = k0 + (int64_t)u * kBinBlock;
+        cells[u] = k < d.n ? d.bin_key[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBinPerThread; ++u) {
+        const int64_t k = k0 + (int64_t)u * kBinBlock;
+        if (k < d.n) {
+            const int s = segment_of(d, k);
+            const int64_t s0 = s ? d.n_tri : 0;
+            const int slot = d.bin_start[s * (kBinCells + 1) + cells[u]] + atomicAdd(d.bin_fill + s * kBinCells + cells[u], 1);
+            d.bin_tmp[s0 + slot] = (int32_t)k;
+        }
+    }
+}
+
+// Writes binned position p: body k's index and its inputs.
+__device__ __forceinline__ void place(const Desc &d, int64_t p, int32_t k) {
+    d.bin_idx[p] = k;
+    d.binned[p] = d.x[k];
+    d.binned[d.n + p] = d.y[k];
+    d.binned[2 * d.n + p] = d.z[k];
+    d.binned[3 * d.n + p] = d.m[k];
+    d.binned[4 * d.n + p] = d.vx[k];
+    d.binned[5 * d.n + p] = d.vy[k];
+    d.binned[6 * d.n + p] = d.vz[k];
+    d.binned[7 * d.n + p] = d.rh[k];
+}
+
+// One cell per wave: its members ordered by index (a bitonic network across
+// the lanes when they fit one wave, else by counting), placed.
+__global__ __launch_bounds__(kBinBlock) void k_bin_order(const Desc d) {
+    const int64_t w = (int64_t)blockIdx.x * (kBinBlock / kWave) + wave_id();
+    if (w >= 2 * kBinCells) return;
+    const int s = (int)(w / kBinCells), c = (int)(w % kBinCells);
+    const int64_t s0 = s ? d.n_tri : 0;
+    const int32_t *start = d.bin_start + s * (kBinCells + 1);
+    const int st = start[c], cnt = start[c + 1] - st;
+    if (cnt == 0) return;
+    const int32_t *m = d.bin_tmp + s0 + st;
+    const int l = lane();
+    if (cnt <= kWave) {
+        int32_t v = l < cnt ? m[l] : INT32_MAX;
+#pragma unroll
+        for (int k = 2; k <= kWave; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const int32_t o = __shfl_xor(v, j);
+                const bool up = (l & k) == 0, lower = (l & j) == 0;
+                v = (up == lower) ? min(v, o) : max(v, o);
+            }
+        if (l < cnt) place(d, s0 + st + l, v);
+    } else {
+        for (int i = l; i < cnt; i += kWave) {
+            const int32_t me = m[i];
+            int rank = 0;
+#pragma unroll 8
+            for (int j = 0; j < cnt; ++j) rank += m[j] < me;
+            place(d, s0 + st + rank, me);
+        }
+    }
+}
+
+// Tile g (one wave): box record of its 64 binned positions.
+__device__ __forceinline__ void box_tile(const Desc &d, int64_t g) {
+    const int l = lane();
+    int64_t pos, end;
+    if (g < d.n_tboxes) {
+        pos = g * kWave + l;
+        end = d.n_tri;
+    } else {
+        pos = d.n_tri + (g - d.n_tboxes) * kWave + l;
+        end = d.n;
+    }
+    const bool valid = pos < end;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid)
+#pragma unroll
+        for (int f = 0; f < 8; ++f) v[f] = d.binned[f * d.n + pos];
+    bool finite = true;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) finite = finite && isfinite(v[f]);
+    const bool bad = __ballot(valid && !finite) != 0;
+    const double rc = d.f * v[7];
+    double r[13];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = valid ? v[a] : INFINITY;
+        r[3 + a] = valid ? v[a] : -INFINITY;
+        r[6 + a] = valid ? v[4 + a] : INFINITY;
+        r[9 + a] = valid ? v[4 + a] : -INFINITY;
+    }
+    r[12] = valid ? kScreenQ * (rc * rc) : 0.0;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 13; ++a) {
+            const double o = __shfl_xor(r[a], off);
+            r[a] = (a < 3 || (a >= 6 && a < 9)) ? fmin(r[a], o) : fmax(r[a], o);
+        }
+    if (l == 0) {
+        double *box = d.tbox_w + g * kBoxDoubles;
+#pragma unroll
+        for (int a = 0; a < 12; ++a) box[a] = r[a];
+        box[12] = bad ? NAN : r[12];
+    }
+}
+
+__global__ __launch_bounds__(kGatherWaves * kWave) void k_bin_boxes(const Desc d) {
+    const int64_t g = (int64_t)blockIdx.x * kGatherWaves + wave_id();
+    if (g < d.n_boxes) box_tile(d, g);
+}
+
+// The six binning launches of one problem.
+hipError_t launch_binning(const Desc &d, hipStream_t stream) {
+    const unsigned chunks = (unsigned)((d.n + kBinChunk - 1) / kBinChunk);
+    hipLaunchKernelGGL(k_bin_bbox, dim3(chunks), dim3(kBinBlock), 0, stream, d);
+    hipLaunchKernelGGL(k_bin_count, dim3(chunks), dim3(kBinBlock), 0, stream, d);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kBinScanThreads), 0, stream, d);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(chunks), dim3(kBinBlock), 0, stream, d);
+    hipLaunchKernelGGL(k_bin_order, dim3((unsigned)(2 * kBinCells / (kBinBlock / kWave))), dim3(kBinBlock), 0,
+                       stream, d);
+    hipLaunchKernelGGL(k_bin_boxes, dim3((unsigned)((d.n_boxes + kGatherWaves - 1) / kGatherWaves)),
+                       dim3(kGatherWaves * kWave), 0, stream, d);
+    return hipGetLastError();
+}
+
 struct FinLds {
     double part[kFinSplit][3][kFinBodies];
     int scan[kMaxBuckets + 1];
@@ -703,14 +1115,14 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     const int tid = threadIdx.x;
     auto &part = F.part;
     const int col = tid % kFinBodies, split = tid / kFinBodies;
-    const int64_t k = lb * kFinBodies + col;
-    const bool own_sum = k < d.n && (k < d.n_tri || d.n_rows == 0);
+    const int64_t pos = lb * kFinBodies + col;  // position in the binned order
+    const bool own_sum = pos < d.n && (pos < d.n_tri || d.n_rows == 0);
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (own_sum) {
         const int64_t per = (d.B + kFinSplit - 1) / kFinSplit;
         const int64_t c0 = split * per;
         const int64_t c1 = (c0 + per) < d.B ? (c0 + per) : d.B;
-        const double *p = d.partial + k;
+        const double *p = d.partial + pos;
 #pragma unroll 8
         for (int64_t c = c0; c < c1; ++c) {
             sx += p[(3 * c) * d.n_tri];
@@ -723,7 +1135,8 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     part[split][2][col] = sz;
     __syncthreads();
     bool nonfinite = false, root_of_group = false;
-    if (split == 0 && k < d.n) {
+    if (split == 0 && pos < d.n) {
+        const int64_t k = d.bidx ? d.bidx[pos] : pos;  // the caller's index
         if (own_sum) {
             for (int s2 = 1; s2 < kFinSplit; ++s2) {
                 sx += part[s2][0][col];
@@ -902,10 +1315,14 @@ void launch_tiles_r(const TileGroup &g, int rot, const Desc &one, const Desc *de
 }  // namespace
 
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
-                       int n_groups, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream, hipEvent_t *ev) {
+                       int n_groups, int n_binned, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
+                       hipEvent_t *ev) {
     const Desc &inl = descs_host[0];
     const Desc *dd = n_desc == 1 ? nullptr : descs_dev;
     if (ev && hipEventRecord(ev[0], stream) != hipSuccess) return hipErrorUnknown;
+    if (n_binned > 0)  // binning of the problems that use it, one problem after the other
+        for (int p = 0; p < n_desc; ++p)
+            if (descs_host[p].bin_idx && launch_binning(descs_host[p], stream) != hipSuccess) return hipErrorUnknown;
     for (int k = 0; k < n_groups; ++k) {
         const TileGroup &g = groups[k];
         if (g.n_tasks <= 0) continue;

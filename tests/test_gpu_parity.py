@@ -19,10 +19,14 @@ DT = dg.DT_HALF_YEAR
 F = dg.RCRIT_FACTOR
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["auto", "binned"])
+def ctx(request):
+    """A context with the default choice of spatial binning (by problem size)
+    and one that bins every problem."""
     from paper_2304_07325_amd import binding as B
     c = B.Context(max_n=100_000, max_pairs=1 << 20)
+    if request.param == "binned":
+        c.set_option(B.OPT_BIN, 2)
     yield c
     c.close()
 
@@ -185,16 +189,17 @@ def _batch_specs():
             (129, 129, 7), (2000, 200, 8), (513, 512, 9), (64, 10, 10), (3001, 3000, 11), (900, 1, 12)]
 
 
-@pytest.mark.parametrize("rows", [0, 2])
-def test_batch_matches_plain_and_oracle(ora, rows):
+@pytest.mark.parametrize("rows,binning", [(0, 0), (2, 0), (0, 2)])
+def test_batch_matches_plain_and_oracle(ora, rows, binning):
     import torch
     from paper_2304_07325_amd import binding as B
     specs = _batch_specs()
     states = [G.dense_state(n, seed=s, box=4.0, n_m=nm) for (n, nm, s) in specs]
     total = sum(n for n, _, _ in specs)
-    G.say("batch", len(specs), "problems", total, "bodies", "rows", rows)
+    G.say("batch", len(specs), "problems", total, "bodies", "rows", rows, "binning", binning)
     ctx = B.Context(max_n=total, max_pairs=sum(max(4 * n, 4096) for n, _, _ in specs))
     ctx.set_option(B.OPT_TILE_ROWS, rows)
+    ctx.set_option(B.OPT_BIN, binning)
     dev = [B.to_device_state(s) for s in states]
     outs = [B.Outputs(n, max(4 * n, 4096)) for n, _, _ in specs]
     probs = [(d, nm, DT, F, o) for d, (n, nm, _), o in zip(dev, specs, outs)]
@@ -210,6 +215,7 @@ def test_batch_matches_plain_and_oracle(ora, rows):
     # are bit-identical to the plain call's whatever else is in the batch
     plain_ctx = B.Context(max_n=max(n for n, _, _ in specs), max_pairs=1 << 16)
     plain_ctx.set_option(B.OPT_TILE_ROWS, rows)
+    plain_ctx.set_option(B.OPT_BIN, binning)
     for (n, nm, _), d, g in zip(specs, dev, got):
         p = G.run_gpu(plain_ctx, {k: v.cpu().numpy() for k, v in d.items()}, nm, DT, F)
         assert p["acc"].tobytes() == g["acc"].tobytes(), "batched acc differs from the plain call"
