@@ -62,7 +62,6 @@ extern "C" {
 /* Context options (symba_set_option). */
 #define SYMBA_OPT_TILE_ROWS 1   /* bodies per lane in triangle tiles: 1, 2 or 4 (0 = automatic) */
 #define SYMBA_OPT_FIELD_ROWS 2  /* field bodies per lane in massive x field tiles: 1 or 2 (0 = automatic) */
-#define SYMBA_OPT_ROTATE 3      /* lane rotation of the j-side sums: 0 = DPP, 1 = ds_bpermute */
 #define SYMBA_OPT_SCREEN 4      /* 0 = FP64 reach screen, 1 = FP32 closest-approach pre-screen */
 #define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
 #define SYMBA_OPT_BIN 6         /* spatial binning: 0 = by problem size, 1 = never, 2 = always */

@@ -41,7 +41,7 @@ struct symba_ctx {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     // options
-    int opt_rows = 0, opt_field_rows = 0, opt_rotate = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0;
+    int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0;
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
     // timing events (SYMBA_OPT_TIMING): three per timed call
@@ -310,10 +310,6 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             if (value != 0 && value != 1 && value != 2) return SYMBA_EINVAL;
             c->opt_field_rows = value;
             return SYMBA_OK;
-        case SYMBA_OPT_ROTATE:
-            if (value != 0 && value != 1) return SYMBA_EINVAL;
-            c->opt_rotate = value;
-            return SYMBA_OK;
         case SYMBA_OPT_BIN:
             if (value < 0 || value > 2) return SYMBA_EINVAL;
             c->opt_bin = value;
@@ -358,10 +354,10 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
     d.stats = c->stats;
-    const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocks, kCloseBlocks};
+    const symba::LaunchCfg cfg{c->opt_screen, kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
-    const symba::TileGroup g{rows, field_rows, 0, 1, 0, d.n_tasks};
+    const symba::TileGroup g{rows, field_rows, binned, 0, 1, 0, d.n_tasks};
     hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, binned, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
@@ -382,16 +378,20 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     // Each problem gets the tile size a single call would give it, so its
     // results do not depend on the rest of the batch; problems are ordered by
     // tile size and each size is one tile-kernel launch.
-    std::vector<int> rows((size_t)n_problems), frows((size_t)n_problems), order((size_t)n_problems);
+    std::vector<int> rows((size_t)n_problems), frows((size_t)n_problems), bins((size_t)n_problems),
+        order((size_t)n_problems);
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
         const int64_t n_tri = q.n_m >= q.n - 1 ? q.n : q.n_m;
         rows[k] = rows_for(c, n_tri);
         frows[k] = field_rows_for(q.n - n_tri, c->opt_field_rows);
+        bins[k] = use_bin(c, q.n, q.n_m) ? 1 : 0;
         order[k] = k;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        return rows[a] != rows[b] ? rows[a] < rows[b] : frows[a] < frows[b];
+        if (rows[a] != rows[b]) return rows[a] < rows[b];
+        if (frows[a] != frows[b]) return frows[a] < frows[b];
+        return bins[a] < bins[b];
     });
     std::vector<Desc> ds((size_t)n_problems);
     std::vector<Plan> plans((size_t)n_problems);
@@ -407,12 +407,13 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0, box_off = 0;
     int n_binned = 0;
     size_t partial_off = 0;
-    const symba::LaunchCfg cfg{c->opt_rotate, c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
+    const symba::LaunchCfg cfg{c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
     for (int32_t s = 0; s < n_problems; ++s) {
         const int k = order[s];
         const symba_problem &q = probs[k];
-        if (groups.empty() || groups.back().rows != rows[k] || groups.back().field_rows != frows[k])
-            groups.push_back(symba::TileGroup{rows[k], frows[k], s, s, task_total, 0});
+        if (groups.empty() || groups.back().rows != rows[k] || groups.back().field_rows != frows[k] ||
+            groups.back().binned != bins[k])
+            groups.push_back(symba::TileGroup{rows[k], frows[k], bins[k], s, s, task_total, 0});
         Desc &d = ds[s];
         fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[s], frows[k]);
         d.task_base = task_total;
@@ -430,7 +431,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.ctr = c->ctr + symba::kCtrSlots * (int64_t)s;
         d.stats = c->stats;
         d.fin_base = fin_total;
-        n_binned += wire_binning(c, d, use_bin(c, q.n, q.n_m), body_off, box_off);
+        n_binned += wire_binning(c, d, bins[k] != 0, body_off, box_off);
         box_off += d.n_boxes;
         task_total += d.n_tasks;
         fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);

@@ -87,17 +87,17 @@ struct Desc {
     int32_t *bin_start;   // [2][2049] cell starts
 };
 
-// Problems [p0, p1) of a launch that share a tile size: their tasks are
+// Problems [p0, p1) of a launch that share a tile size and binning: their tasks are
 // [task_begin, task_begin + n_tasks) of the launch's task numbering.
 struct TileGroup {
     int rows;        // 1, 2 or 4
     int field_rows;  // 1 or 2
+    int binned;      // 1: the problems are binned
     int p0, p1;
     int64_t task_begin, n_tasks;
 };
 
 struct LaunchCfg {
-    int rotate;      // 0 DPP, 1 ds_bpermute
     int screen;      // 0 FP64 reach screen, 1 FP32 pre-screen
     int scatter_blocks_per_problem;  // pair-scatter blocks per problem (final kernel)
     int close_blocks_per_problem;    // closing-kernel blocks per problem

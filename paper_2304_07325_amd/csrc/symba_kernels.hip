@@ -217,13 +217,19 @@ __device__ __forceinline__ void uf_unite(int32_t *up, int a, int b) {
 // the canonical (lexicographic) pair order is bucket by bucket.
 __device__ __forceinline__ int bucket_of(const Desc &d, int a) { return (int)(((int64_t)a * d.nb) / d.n); }
 
-// Exact test of one candidate per lane (wave-collective): flagged pairs are
-// appended (wave ballot + prefix, one atomic per wave) and grouped at once.
+// Exact test of one candidate per lane (wave-collective), given as positions
+// in the order the tile kernel reads (the binned copy holds the same values):
+// flagged pairs are reported by the caller's indices, appended (wave ballot +
+// prefix, one atomic per wave) and grouped at once.
 __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i, int j) {
     bool flag = false;
     if (valid && i < d.n && j < d.n)
-        flag = encounter_test(d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i], d.vx[j] - d.vx[i],
-                              d.vy[j] - d.vy[i], d.vz[j] - d.vz[i], d.rh[i], d.rh[j], d.f, d.dt);
+        flag = encounter_test(d.bx[j] - d.bx[i], d.by[j] - d.by[i], d.bz[j] - d.bz[i], d.bvx[j] - d.bvx[i],
+                              d.bvy[j] - d.bvy[i], d.bvz[j] - d.bvz[i], d.brh[i], d.brh[j], d.f, d.dt);
+    if (flag && d.bidx) {  // binned position -> caller's index
+        i = d.bidx[i];
+        j = d.bidx[j];
+    }
     const int a = i < j ? i : j, b = i < j ? j : i;
     const unsigned long long fm = __ballot(flag);
     if (fm == 0) return;
@@ -243,19 +249,14 @@ __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i,
     }
 }
 
-// Exact test of up to 64 queued candidates, one per lane (queued as binned
-// positions, tested and reported by the caller's indices).
+// Exact test of up to 64 queued candidates (positions), one per lane.  A
+// padding position, possible only next to a non-finite body, is out of range
+// and rejected by the test.
 __device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
     if (lane() == 0) atomicAdd(d.stats + kStatCandidates, (unsigned long long)count);
     const bool mine = lane() < count;
     uint2 c = make_uint2(0u, 0u);
-    if (mine) {
-        c = Q.q[(head + lane()) & Q.mask];
-        // binned -> caller's order (a padding position, possible only next to a
-        // non-finite body, stays out of range and is rejected by the test)
-        if (d.bidx && c.x < (unsigned)d.n && c.y < (unsigned)d.n)
-            c = make_uint2((unsigned)d.bidx[c.x], (unsigned)d.bidx[c.y]);
-    }
+    if (mine) c = Q.q[(head + lane()) & Q.mask];
     test_and_group(d, mine, (int)c.x, (int)c.y);
 }
 
@@ -395,13 +396,6 @@ __device__ __forceinline__ double rotate_dpp(double v) {
     return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double rotate_bperm(double v, int addr) {
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_ds_bpermute(addr, lo);
-    hi = __builtin_amdgcn_ds_bpermute(addr, hi);
-    return __hiloint2double(hi, lo);
-}
-
 template <int R>
 struct Slots {
     Body b[R];
@@ -444,12 +438,11 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
 // tile entry (l + t0) mod 64 and ends with those of entry (l + t0 + 16) mod 64.
 // Steps whose screen passed anywhere in the wave are only marked in a scalar
 // bit mask; the candidates are pushed afterwards (no branch in the loop).
-template <int R, int RS, int NACT, int ROT, bool SCR>
+template <int R, int RS, int NACT, bool SCR>
 __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> &L, int q, Slots<R> &S,
                                                int64_t ib, int64_t js, int t0, Queue &Q, double &ajx,
                                                double &ajy, double &ajz) {
     const int l = lane();
-    const int baddr = ((l + 1) & (kWave - 1)) << 2;
     ajx = ajy = ajz = 0.0;
     unsigned pending = 0;
     Body Jn = SCR ? tile_body(L, q, l + t0) : tile_pos(L, q, l + t0);
@@ -476,15 +469,9 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
                 any |= __builtin_amdgcn_ballot_w64(screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q));
         }
         if (SCR) pending |= nonzero(any) << u;
-        if (ROT == 0) {
-            ajx = rotate_dpp(ajx);
-            ajy = rotate_dpp(ajy);
-            ajz = rotate_dpp(ajz);
-        } else {
-            ajx = rotate_bperm(ajx, baddr);
-            ajy = rotate_bperm(ajy, baddr);
-            ajz = rotate_bperm(ajz, baddr);
-        }
+        ajx = rotate_dpp(ajx);
+        ajy = rotate_dpp(ajy);
+        ajz = rotate_dpp(ajz);
     }
     while (pending) {
         const int u = __builtin_ctz(pending);
@@ -530,24 +517,25 @@ __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> 
     }
 }
 
-template <int R, int RS, int ROT, int QS>
+template <int R, int RS, int QS>
 __device__ __forceinline__ void diagonal_tiles(const Desc &d, const TaskLds<RS> &L, Slots<R> &S, int64_t ib,
                                                int t0, Queue &Q, double (&aj)[R][3]) {
     if constexpr (QS < R) {
         if constexpr (QS > 0)
-            rotation_range<R, RS, QS, ROT, true>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0],
-                                                 aj[QS][1], aj[QS][2]);
+            rotation_range<R, RS, QS, true>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0], aj[QS][1],
+                                            aj[QS][2]);
         else
             aj[0][0] = aj[0][1] = aj[0][2] = 0.0;
         diagonal_range<R, RS, QS>(d, L, S, ib, t0, Q);
-        diagonal_tiles<R, RS, ROT, QS + 1>(d, L, S, ib, t0, Q, aj);
+        diagonal_tiles<R, RS, QS + 1>(d, L, S, ib, t0, Q, aj);
     }
 }
 
 // Block pair (I, J) of the folded triangle, by the four waves of the
 // workgroup.  Partial sums land in slot J for the stationary bodies of block
 // I and in slot I for the bodies of block J (slot I for both when I == J).
-template <int R, int RS, int ROT>
+// BIN: the problem is binned, so tile pairs that cannot meet run screen-free.
+template <int R, int RS, bool BIN>
 __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t I,
                                               int64_t J) {
     const int l = lane(), w = wave_id();
@@ -562,7 +550,7 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     // lane r R + q decides stationary tile r against streamed tile q (the box
     // loads overlap the body loads); bit q of free_q: screen-free tile q
     unsigned free_q = 0;
-    if (d.tbox != nullptr && I != J) {
+    if (BIN && I != J) {
         const bool apart = l >= R * R || tiles_apart(d, tri_box(d, I * R + l / R), tri_box(d, J * R + l % R));
         const unsigned long long m = __ballot(apart);
 #pragma unroll
@@ -579,15 +567,15 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     if (I != J) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            if ((free_q >> q) & 1u)
-                rotation_range<R, RS, R, ROT, false>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0],
-                                                     aj[q][1], aj[q][2]);
+            if (BIN && ((free_q >> q) & 1u))
+                rotation_range<R, RS, R, !BIN>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                                               aj[q][2]);
             else
-                rotation_range<R, RS, R, ROT, true>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0],
-                                                    aj[q][1], aj[q][2]);
+                rotation_range<R, RS, R, true>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                                               aj[q][2]);
         }
     } else {
-        diagonal_tiles<R, RS, ROT, 0>(d, L, S, ib, t0, Q, aj);
+        diagonal_tiles<R, RS, 0>(d, L, S, ib, t0, Q, aj);
     }
     __syncthreads();  // every wave is done with the tiles
     const int jend = (l + t0 + kSteps) & (kWave - 1);
@@ -658,7 +646,7 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
 // Field block fb against every massive row, by the four waves of the
 // workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
 // pairs; the field accelerations are complete at the end and written directly.
-template <int RF, int RS>
+template <int RF, int RS, bool BIN>
 __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb) {
     const int l = lane(), w = wave_id();
     const int t0 = w * kSteps;
@@ -675,7 +663,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         const int nq = left >= RS * kWave ? RS : (int)((left + kWave - 1) / kWave);
         // lane q RF + r decides field tile r against massive tile q of the chunk
         unsigned free_q = 0;
-        if (d.tbox != nullptr) {
+        if (BIN) {
             const bool apart = l >= nq * RF ||
                                tiles_apart(d, field_box(d, fb * RF + l % RF), tri_box(d, s0 / kWave + l / RF));
             const unsigned long long m = __ballot(apart);
@@ -689,8 +677,8 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         stage(d, L, s0, nq, d.n_rows);
         __syncthreads();
         for (int q = 0; q < nq; ++q) {
-            const bool apart = (free_q >> q) & 1u;
-            unsigned pending = apart ? field_range<RF, RS, false>(d, L, q, s0, t0, fbody, ax, ay, az)
+            const bool apart = BIN && ((free_q >> q) & 1u);
+            unsigned pending = apart ? field_range<RF, RS, !BIN>(d, L, q, s0, t0, fbody, ax, ay, az)
                                      : field_range<RF, RS, true>(d, L, q, s0, t0, fbody, ax, ay, az);
             while (pending) {
                 const int u = __builtin_ctz(pending);
@@ -752,9 +740,19 @@ __device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, int
     return lo;
 }
 
-template <int R, int RF, int ROT>
-__device__ __forceinline__ void run_task(const Desc &d, int64_t t) {
+template <int R, int RF, bool BIN>
+__device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
     constexpr int RS = R > RF ? R : RF;
+    // Without binning the tile kernel's inputs are the caller's arrays and no
+    // index map or box exists: said here at compile time, so that the unbinned
+    // kernel keeps no registers for them.
+    Desc d = desc;
+    if (!BIN) {
+        d.bx = desc.x; d.by = desc.y; d.bz = desc.z; d.bm = desc.m;
+        d.bvx = desc.vx; d.bvy = desc.vy; d.bvz = desc.vz; d.brh = desc.rh;
+        d.bidx = nullptr;
+        d.tbox = nullptr;
+    }
     __shared__ TaskLds<RS> L;
     __shared__ uint2 qbuf[kTaskWaves][queue_cap(RS)];
     Queue Q{qbuf[wave_id()], queue_cap(RS) - 1, 0, 0};
@@ -762,26 +760,26 @@ __device__ __forceinline__ void run_task(const Desc &d, int64_t t) {
     if (lt < d.n_tri_tasks) {
         int64_t I, J;
         fold_decode(d.B, lt, I, J);
-        triangle_task<R, RS, ROT>(d, L, Q, I, J);
+        triangle_task<R, RS, BIN>(d, L, Q, I, J);
     } else {
-        field_task<RF, RS>(d, L, Q, lt - d.n_tri_tasks);
+        field_task<RF, RS, BIN>(d, L, Q, lt - d.n_tri_tasks);
     }
 }
 
 // One problem: the descriptor is a kernel argument (scalar registers).
-template <int R, int RF, int ROT>
+template <int R, int RF, bool BIN>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles(const Desc d) {
-    run_task<R, RF, ROT>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
+    run_task<R, RF, BIN>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
 }
 
 // Many problems of one tile size: every block finds its problem by the task
 // bases (descs is the group's slice of the launch's descriptors).
-template <int R, int RF, int ROT>
+template <int R, int RF, bool BIN>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles_batch(const Desc *__restrict__ descs, int n_desc, int64_t task_begin) {
     const int64_t t = task_begin + blockIdx.x;
-    run_task<R, RF, ROT>(descs[problem_of(descs, n_desc, t, 0)], t);
+    run_task<R, RF, BIN>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1292,23 +1290,23 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_close_batch(const Desc *__
     close_block(descs[blockIdx.x / blocks], blockIdx.x % blocks, blocks);
 }
 
-template <int R, int RF, int ROT>
+template <int R, int RF, bool BIN>
 void launch_tiles(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
     if (descs)
-        hipLaunchKernelGGL((k_tiles_batch<R, RF, ROT>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream,
+        hipLaunchKernelGGL((k_tiles_batch<R, RF, BIN>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream,
                            descs + g.p0, g.p1 - g.p0, g.task_begin);
     else
-        hipLaunchKernelGGL((k_tiles<R, RF, ROT>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream, one);
+        hipLaunchKernelGGL((k_tiles<R, RF, BIN>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream, one);
 }
 
 template <int R>
-void launch_tiles_r(const TileGroup &g, int rot, const Desc &one, const Desc *descs, hipStream_t stream) {
+void launch_tiles_r(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
     if (g.field_rows == 2) {
-        if (rot) launch_tiles<R, 2, 1>(g, one, descs, stream);
-        else launch_tiles<R, 2, 0>(g, one, descs, stream);
+        if (g.binned) launch_tiles<R, 2, true>(g, one, descs, stream);
+        else launch_tiles<R, 2, false>(g, one, descs, stream);
     } else {
-        if (rot) launch_tiles<R, 1, 1>(g, one, descs, stream);
-        else launch_tiles<R, 1, 0>(g, one, descs, stream);
+        if (g.binned) launch_tiles<R, 1, true>(g, one, descs, stream);
+        else launch_tiles<R, 1, false>(g, one, descs, stream);
     }
 }
 
@@ -1327,9 +1325,9 @@ hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc
         const TileGroup &g = groups[k];
         if (g.n_tasks <= 0) continue;
         switch (g.rows) {
-            case 1: launch_tiles_r<1>(g, cfg.rotate, inl, dd, stream); break;
-            case 2: launch_tiles_r<2>(g, cfg.rotate, inl, dd, stream); break;
-            default: launch_tiles_r<4>(g, cfg.rotate, inl, dd, stream); break;
+            case 1: launch_tiles_r<1>(g, inl, dd, stream); break;
+            case 2: launch_tiles_r<2>(g, inl, dd, stream); break;
+            default: launch_tiles_r<4>(g, inl, dd, stream); break;
         }
         if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
     }

@@ -57,18 +57,18 @@ def test_small_dense(ctx, ora, n, n_m):
 
 
 @pytest.mark.parametrize("rows", [1, 2, 4])
-@pytest.mark.parametrize("rotate", [0, 1])
-def test_tile_options(ctx, ora, rows, rotate):
+@pytest.mark.parametrize("field_rows", [1, 2])
+def test_tile_options(ctx, ora, rows, field_rows):
     from paper_2304_07325_amd import binding as B
     ctx.set_option(B.OPT_TILE_ROWS, rows)
-    ctx.set_option(B.OPT_ROTATE, rotate)
+    ctx.set_option(B.OPT_FIELD_ROWS, field_rows)
     try:
         for n, n_m in ((777, 776), (1100, 300), (530, 530)):
             s = G.dense_state(n, seed=7 * n + rows, box=3.0, n_m=n_m)
-            compare(ctx, ora, s, n_m, label=f"rows={rows} rotate={rotate}")
+            compare(ctx, ora, s, n_m, label=f"rows={rows} field_rows={field_rows}")
     finally:
         ctx.set_option(B.OPT_TILE_ROWS, 0)
-        ctx.set_option(B.OPT_ROTATE, 0)
+        ctx.set_option(B.OPT_FIELD_ROWS, 0)
 
 
 @pytest.mark.parametrize("k", [0, 1, 7, 19])
