@@ -249,9 +249,9 @@ __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i,
     }
 }
 
-// Exact test of up to 64 queued candidates (positions), one per lane.  A
-// padding position, possible only next to a non-finite body, is out of range
-// and rejected by the test.
+// Exact test of up to 64 queued candidates (positions), one per lane.  The
+// revisits never queue padding of the triangle; a field task's padding past n
+// is rejected by the test's range check.
 __device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
     if (lane() == 0) atomicAdd(d.stats + kStatCandidates, (unsigned long long)count);
     const bool mine = lane() < count;
@@ -426,9 +426,12 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
         const Body &I = S.b[r];
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-        const bool c = screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+        // padding past n_tri (which may hold field bodies' positions) never
+        // becomes a candidate, even next to a body with an infinite q
+        const int64_t i = ib + r * kWave + l;
+        const bool c = i < d.n_tri && j < d.n_tri && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
         const unsigned long long mask = __ballot(c);
-        if (mask) push(Q, mask, c, ib + r * kWave + l, j);
+        if (mask) push(Q, mask, c, i, j);
     }
     maybe_drain(d, Q);
 }
@@ -510,9 +513,11 @@ __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> 
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
-        const bool c = owner && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+        const int64_t i = ib + QS * kWave + l, j = ib + QS * kWave + ((l + t) & (kWave - 1));
+        const bool c = owner && i < d.n_tri && j < d.n_tri &&
+                       screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
         const unsigned long long mask = __ballot(c);
-        if (mask) push(Q, mask, c, ib + QS * kWave + l, ib + QS * kWave + ((l + t) & (kWave - 1)));
+        if (mask) push(Q, mask, c, i, j);
         maybe_drain(d, Q);
     }
 }

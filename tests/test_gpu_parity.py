@@ -383,3 +383,24 @@ def test_screen_statistics(ctx):
     assert flagged == 3 * res[0]["n_pairs"]
     assert cands >= flagged
     assert ctx.read_stats() == (0, 0, 0)
+
+
+def test_nonfinite_inputs_match_oracle(ctx, ora):
+    """A field body at an infinite position, a massive body with a NaN
+    velocity and one with an infinite Hill radius: the flagged pairs and
+    groups still match the oracle exactly (the screen passes non-finite pairs
+    on to the exact test), the status reports the non-finite acceleration
+    (the infinite field body's), and every finite acceleration is exact."""
+    s = G.dense_state(400, seed=17, box=2.0, n_m=300)
+    s["x"][350] = np.inf
+    s["vy"][77] = np.nan
+    s["rh"][200] = np.inf
+    G.say("non-finite inputs")
+    gpu = G.run_gpu(ctx, s, 300, DT, F)
+    ref = ora.kick_encounter(s, 300, DT, F)
+    assert gpu["status"] & 2
+    assert np.array_equal(gpu["pair_i"], ref["pair_i"]) and np.array_equal(gpu["pair_j"], ref["pair_j"])
+    assert np.array_equal(gpu["group_id"], ref["group_id"]) and gpu["n_groups"] == ref["n_groups"]
+    fin = np.isfinite(ref["acc"]).all(axis=1)
+    assert fin.sum() == 399 and not np.isfinite(gpu["acc"][350]).all()
+    G.check_acc(s, 300, gpu["acc"][fin], ref["acc"][fin], bodies=np.nonzero(fin)[0])
