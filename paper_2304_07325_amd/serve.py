@@ -130,25 +130,8 @@ class Server:
         return s.resident_bytes + s.scratch
 
     def _pick(self, pending: deque):
-        """Splits `pending` into the requests of the next call and the rest:
-        in arrival order, a request joins if its simulation is not in the call
-        yet and the call still fits the body bound and the budget."""
-        batch, chosen, rest = [], set(), deque()
-        bodies = need = caps = 0
-        for req in pending:
-            k = req[1]
-            s = self.sims[k]
-            cap = pair_capacity(s.n)
-            if (k not in chosen and bodies + s.n <= self.max_batch_bodies and caps + cap <= self.max_pairs and
-                    len(batch) < 4096 and need + self._need(k) <= self.budget):
-                batch.append(req)
-                chosen.add(k)
-                bodies += s.n
-                caps += cap
-                need += self._need(k)
-            else:
-                rest.append(req)
-        return batch, rest
+        return pick_batch(pending, [s.n for s in self.sims], [self._need(k) for k in range(len(self.sims))],
+                          self.budget, self.max_batch_bodies, self.max_pairs)
 
     def run_batch(self, sim_ids, stream=None):
         """One batched call over distinct simulations, loading the ones that are
@@ -219,6 +202,30 @@ class Server:
                     pairs_per_s=float(pairs / span) if span > 0 else 0.0,
                     uploads=self.uploads, evictions=self.evictions,
                     budget_bytes=self.budget + self.fixed_bytes)
+
+
+def pick_batch(pending, sizes, needs, budget: int, max_bodies: int, max_pairs: int):
+    """Splits `pending` (an iterable of (request, simulation) in arrival order)
+    into the requests of the next call and the rest.  A request joins if its
+    simulation is not in the call yet and the call stays within max_bodies
+    bodies, max_pairs of output pair capacity, 4096 problems and `budget`
+    bytes of device memory (`needs[k]`: resident bytes plus library scratch
+    of simulation k)."""
+    batch, chosen, rest = [], set(), deque()
+    bodies = need = caps = 0
+    for req in pending:
+        k = req[1]
+        cap = pair_capacity(sizes[k])
+        if (k not in chosen and bodies + sizes[k] <= max_bodies and caps + cap <= max_pairs and
+                len(batch) < 4096 and need + needs[k] <= budget):
+            batch.append(req)
+            chosen.add(k)
+            bodies += sizes[k]
+            caps += cap
+            need += needs[k]
+        else:
+            rest.append(req)
+    return batch, rest
 
 
 def _pairs(s: _Sim) -> int:
