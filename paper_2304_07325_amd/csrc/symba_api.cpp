@@ -95,8 +95,15 @@ int field_rows_for(int64_t n_field, int opt) {
     return n_field >= 200000 ? 2 : 1;
 }
 
+// Split diagonals of the folded triangle (tile pairs launched last to even
+// out the end of the tile kernel).  A tuning knob.
+#ifndef SYMBA_TAIL_SPLIT
+#define SYMBA_TAIL_SPLIT 2
+#endif
+
 struct Plan {
-    int64_t n_rows, n_tri, B, n_tri_tasks, n_field_tasks, n_blk;
+    int64_t n_rows, n_tri, B, n_split, n_whole, n_slots, n_tri_tasks, n_field_tasks, n_blk;
+    int rows;
     size_t partial_doubles;
 };
 
@@ -106,13 +113,17 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
     p.n_tri = n_m >= n - 1 ? n : n_m;
     const int64_t S = (int64_t)rows * symba::kWave;
     const int64_t F = (int64_t)field_rows * symba::kWave;
+    p.rows = rows;
     if (p.n_rows > 0) {
         p.B = (p.n_tri + S - 1) / S;
-        p.n_tri_tasks = symba::fold_count(p.B);
+        p.n_split = symba::split_diagonals(p.B, rows, SYMBA_TAIL_SPLIT);
+        p.n_whole = symba::whole_count(p.B, p.n_split);
+        p.n_tri_tasks = p.n_whole + p.n_split * p.B * rows * rows;
+        p.n_slots = symba::partial_slots(p.B, rows, p.n_split);
         p.n_field_tasks = (n - p.n_tri + F - 1) / F;
     }
     p.n_blk = (n + symba::kFinBodies - 1) / symba::kFinBodies;
-    p.partial_doubles = (size_t)p.B * 3 * (size_t)p.n_tri;
+    p.partial_doubles = (size_t)p.n_slots * 3 * (size_t)p.n_tri;
     return p;
 }
 
@@ -198,7 +209,8 @@ void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int
     d.n = n; d.n_rows = p.n_rows; d.n_tri = p.n_tri; d.dt = dt; d.f = f;
     d.k15 = 1.5; d.k1875 = 1.875;
     d.screen_dt2 = 2.0 * (1.0 + 0x1p-20) * (dt * dt);
-    d.B = p.B; d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
+    d.B = p.B; d.n_split = p.n_split; d.n_whole = p.n_whole; d.n_slots = p.n_slots;
+    d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
     d.n_blk = p.n_blk; d.field_block = (int64_t)field_rows * symba::kWave;
     (void)n_m;
 }
@@ -487,12 +499,17 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
     const int64_t total = p.n_tri_tasks + p.n_field_tasks;
     for (int64_t f = 0; f < std::min(total, cap); ++f) {
         const int64_t t = symba::task_in_order(p.n_tri_tasks, total, f);
-        if (t < p.n_tri_tasks) {
+        if (t < p.n_whole) {
             int64_t I, J;
-            symba::fold_decode(p.B, t, I, J);
+            symba::whole_decode(p.B, p.n_split, t, I, J);
             tasks[3 * f] = 0;
             tasks[3 * f + 1] = I;
             tasks[3 * f + 2] = J;
+        } else if (t < p.n_tri_tasks) {
+            const symba::SplitTask T = symba::split_decode(p.B, rows, t - p.n_whole);
+            tasks[3 * f] = 2;
+            tasks[3 * f + 1] = T.I * rows + T.r;
+            tasks[3 * f + 2] = T.J * rows + T.q;
         } else {
             tasks[3 * f] = 1;
             tasks[3 * f + 1] = t - p.n_tri_tasks;

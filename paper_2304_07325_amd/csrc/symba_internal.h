@@ -54,7 +54,10 @@ struct Desc {
     double screen_dt2;    // 2 (1 + 2^-20) dt^2, the screen's velocity term
     // plan
     int64_t B;            // triangle blocks of 64*rows bodies
-    int64_t n_tri_tasks;  // folded block pairs
+    int64_t n_split;      // split diagonals D of the folded triangle
+    int64_t n_whole;      // whole block pairs of the folded triangle (launched first)
+    int64_t n_slots;      // partial-sum slots per body: B + 2 D (rows - 1), D split diagonals
+    int64_t n_tri_tasks;  // whole block pairs + tile pairs of the split diagonals
     int64_t n_tasks;      // triangle + field tasks
     int64_t task_base;    // first global task of this problem
     int64_t n_blk;        // body blocks of this problem's final kernel (kFinBodies bodies each)
@@ -63,7 +66,7 @@ struct Desc {
     int64_t n_boxes;      // all tiles (massive, then field [n_tri, n))
     int64_t field_block;  // field bodies per field task (64*field_rows)
     // scratch slices (context-owned)
-    double *partial;      // [B][3][n_tri] per-slot partial sums
+    double *partial;      // [n_slots][3][n_tri] per-slot partial sums
     int32_t *parent;      // [n] union-find forest as offsets to the parent (0 = root), zero between calls
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
     int2 *pairs;          // [pair_scratch_cap] flagged pairs as found, (min, max)
@@ -103,15 +106,50 @@ struct LaunchCfg {
     int close_blocks_per_problem;    // closing-kernel blocks per problem
 };
 
-// Folded triangle: task t of B blocks -> block pair (I, J); every unordered
-// block pair, diagonal included, appears once and every block row gets the
-// same number of tasks (the triangle mapped onto a rectangle).
-__host__ __device__ inline void fold_decode(int64_t B, int64_t t, int64_t &I, int64_t &J) {
-    const int64_t K = (B - 1) / 2 + 1;
+// Folded triangle: block pair (I, J) with J = I + k (mod B) for offsets
+// k = 0 .. K - 1, K = (B - 1) / 2 + 1, plus, when B is even, the pairs
+// (I, I + B / 2) for I < B / 2: every unordered block pair, diagonal
+// included, appears once and every block row gets the same number of tasks
+// (the triangle mapped onto a rectangle).
+__host__ __device__ inline int64_t fold_offsets(int64_t B) { return (B - 1) / 2 + 1; }
+
+__host__ __device__ inline int64_t fold_count(int64_t B) {
+    if (B <= 0) return 0;
+    return B * fold_offsets(B) + ((B % 2 == 0) ? B / 2 : 0);
+}
+
+// Tail split.  The block pairs of offsets 1 .. D (D split diagonals, at most
+// K - 1) are not run whole: each is cut into its R x R tile pairs (stationary
+// tile r of block I against tile q of block J), run as separate small tasks
+// after all whole block pairs, so that the end of the launch is made of short
+// tasks that even out the finishing times of the workgroups.  A body's
+// partial sums then come from more tasks than there are blocks: tile pair
+// (r, q) of the split pair at offset k writes the sums of its stationary
+// bodies to slot J when q = 0, else to extra slot B + (k - 1) 2 (R - 1) + q - 1,
+// and those of its streamed bodies to slot I when r = 0, else to extra slot
+// B + (k - 1) 2 (R - 1) + (R - 1) + r - 1.  On a split diagonal every block is
+// the stationary block of one pair and the streamed block of another, so every
+// body receives every one of the B + 2 D (R - 1) slots exactly once.
+__host__ __device__ inline int64_t split_diagonals(int64_t B, int R, int64_t want) {
+    if (R < 2 || B < 3) return 0;
+    const int64_t most = fold_offsets(B) - 1;
+    return want < most ? want : most;
+}
+
+__host__ __device__ inline int64_t partial_slots(int64_t B, int R, int64_t D) { return B + 2 * D * (R - 1); }
+
+// Whole block pairs of a folded triangle with D split diagonals.
+__host__ __device__ inline int64_t whole_count(int64_t B, int64_t D) { return fold_count(B) - D * B; }
+
+// Whole task t (t < whole_count) -> block pair (I, J): offset 0, then the
+// offsets past the split ones, then the even-B extra pairs.
+__host__ __device__ inline void whole_decode(int64_t B, int64_t D, int64_t t, int64_t &I, int64_t &J) {
+    const int64_t K = fold_offsets(B) - D;
     const int64_t main_tasks = B * K;
     if (t < main_tasks) {
         I = t / K;
-        J = I + t % K;
+        const int64_t kk = t % K;
+        J = I + (kk == 0 ? 0 : kk + D);
         if (J >= B) J -= B;
     } else {
         I = t - main_tasks;
@@ -119,9 +157,28 @@ __host__ __device__ inline void fold_decode(int64_t B, int64_t t, int64_t &I, in
     }
 }
 
-__host__ __device__ inline int64_t fold_count(int64_t B) {
-    if (B <= 0) return 0;
-    return B * ((B - 1) / 2 + 1) + ((B % 2 == 0) ? B / 2 : 0);
+// Split task s (s < D B R^2) -> block pair (I, J) at offset k, stationary tile
+// r of I, streamed tile q of J, and the partial slots of the two sides.
+struct SplitTask {
+    int64_t I, J, k;
+    int r, q;
+    int64_t slot_i, slot_j;
+};
+
+__host__ __device__ inline SplitTask split_decode(int64_t B, int R, int64_t s) {
+    SplitTask t;
+    const int64_t pair = s / (R * R);
+    const int sub = (int)(s % (R * R));
+    t.r = sub / R;
+    t.q = sub % R;
+    t.k = pair / B + 1;
+    t.I = pair % B;
+    t.J = t.I + t.k;
+    if (t.J >= B) t.J -= B;
+    const int64_t extra = B + (t.k - 1) * 2 * (R - 1);
+    t.slot_i = t.q == 0 ? t.J : extra + t.q - 1;
+    t.slot_j = t.r == 0 ? t.I : extra + (R - 1) + t.r - 1;
+    return t;
 }
 
 // Order in which a single problem's tasks are launched (position f of the

@@ -536,6 +536,47 @@ __device__ __forceinline__ void diagonal_tiles(const Desc &d, const TaskLds<RS> 
     }
 }
 
+// Sums of the four waves' partial accelerations of a task in a fixed order,
+// written to the partial slots: the first NR stationary tiles (bodies from
+// base_i) to slot slot_i, the streamed ones (from base_j) to slot slot_j.  A
+// diagonal block pair (diag) has one set of bodies: both sides are added and
+// written to slot_i.  Called after a barrier that ends every wave's use of
+// the tiles (the sums reuse their LDS).
+template <int R, int RS, int NR>
+__device__ __forceinline__ void write_sums(const Desc &d, TaskLds<RS> &L, const Slots<R> &S,
+                                           const double (&aj)[R][3], int t0, bool diag, int64_t slot_i,
+                                           int64_t base_i, int64_t slot_j, int64_t base_j) {
+    const int l = lane(), w = wave_id();
+    const int jend = (l + t0 + kSteps) & (kWave - 1);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        L.comb[0][w][r][0][l] = S.ax[r];
+        L.comb[0][w][r][1][l] = S.ay[r];
+        L.comb[0][w][r][2][l] = S.az[r];
+        L.comb[1][w][r][0][jend] = aj[r][0];
+        L.comb[1][w][r][1][jend] = aj[r][1];
+        L.comb[1][w][r][2][jend] = aj[r][2];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * NR * kWave; e += kTaskThreads) {
+        const int side = e / (NR * kWave), idx = e % (NR * kWave), r = idx / kWave, ll = idx % kWave;
+        if (diag && side == 1) continue;
+        double sum[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double v = 0.0;
+            for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[side][ww][r][c][ll];
+            if (diag)
+                for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[1][ww][r][c][ll];
+            sum[c] = v;
+        }
+        if (side == 0)
+            write_partial(d, slot_i, base_i + idx, sum[0], sum[1], sum[2]);
+        else
+            write_partial(d, slot_j, base_j + idx, sum[0], sum[1], sum[2]);
+    }
+}
+
 // Block pair (I, J) of the folded triangle, by the four waves of the
 // workgroup.  Partial sums land in slot J for the stationary bodies of block
 // I and in slot I for the bodies of block J (slot I for both when I == J).
@@ -583,37 +624,37 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
         diagonal_tiles<R, RS, 0>(d, L, S, ib, t0, Q, aj);
     }
     __syncthreads();  // every wave is done with the tiles
-    const int jend = (l + t0 + kSteps) & (kWave - 1);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        L.comb[0][w][r][0][l] = S.ax[r];
-        L.comb[0][w][r][1][l] = S.ay[r];
-        L.comb[0][w][r][2][l] = S.az[r];
-        L.comb[1][w][r][0][jend] = aj[r][0];
-        L.comb[1][w][r][1][jend] = aj[r][1];
-        L.comb[1][w][r][2][jend] = aj[r][2];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 2 * R * kWave; e += kTaskThreads) {
-        const int side = e / (R * kWave), idx = e % (R * kWave), r = idx / kWave, ll = idx % kWave;
-        if (I == J && side == 1) continue;
-        double sum[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double v = 0.0;
-            for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[side][ww][r][c][ll];
-            if (I == J)
-                for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[1][ww][r][c][ll];
-            sum[c] = v;
-        }
-        if (side == 0)
-            write_partial(d, J, ib + idx, sum[0], sum[1], sum[2]);
-        else
-            write_partial(d, I, jb + idx, sum[0], sum[1], sum[2]);
-    }
+    write_sums<R, RS, R>(d, L, S, aj, t0, I == J, J, ib, I, jb);
     // The candidates left in this wave's queue are tested last, after the
     // workgroup's barriers, so the other waves never wait on the test's
     // memory round trips.
+    drain_rest(d, Q);
+}
+
+// Tile pair of a split diagonal (see split_decode): stationary tile r of
+// block I against streamed tile q of block J, both sides accumulated, by the
+// four waves of the workgroup as in a whole block pair.
+template <int R, int RS, bool BIN>
+__device__ __forceinline__ void split_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t s) {
+    const int l = lane(), w = wave_id();
+    const int t0 = w * kSteps;
+    const SplitTask T = split_decode(d.B, R, s);
+    const int64_t ib = (T.I * R + T.r) * kWave, jb = (T.J * R + T.q) * kWave;
+    Slots<R> S;
+    S.b[0] = load_body<true>(d, ib + l, d.n_tri);
+    S.ax[0] = S.ay[0] = S.az[0] = 0.0;
+    bool apart = false;
+    if (BIN) apart = __builtin_amdgcn_readfirstlane(
+                         tiles_apart(d, tri_box(d, T.I * R + T.r), tri_box(d, T.J * R + T.q)) ? 1 : 0) != 0;
+    stage(d, L, jb, 1, d.n_tri);
+    __syncthreads();
+    double aj[R][3];
+    if (BIN && apart)
+        rotation_range<R, RS, 1, !BIN>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+    else
+        rotation_range<R, RS, 1, true>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+    __syncthreads();  // every wave is done with the tile
+    write_sums<R, RS, 1>(d, L, S, aj, t0, false, T.slot_i, ib, T.slot_j, jb);
     drain_rest(d, Q);
 }
 
@@ -762,10 +803,12 @@ __device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
     __shared__ uint2 qbuf[kTaskWaves][queue_cap(RS)];
     Queue Q{qbuf[wave_id()], queue_cap(RS) - 1, 0, 0};
     const int64_t lt = t - d.task_base;
-    if (lt < d.n_tri_tasks) {
+    if (lt < d.n_whole) {
         int64_t I, J;
-        fold_decode(d.B, lt, I, J);
+        whole_decode(d.B, d.n_split, lt, I, J);
         triangle_task<R, RS, BIN>(d, L, Q, I, J);
+    } else if (lt < d.n_tri_tasks) {
+        split_task<R, RS, BIN>(d, L, Q, lt - d.n_whole);
     } else {
         field_task<RF, RS, BIN>(d, L, Q, lt - d.n_tri_tasks);
     }
@@ -1122,9 +1165,9 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     const bool own_sum = pos < d.n && (pos < d.n_tri || d.n_rows == 0);
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (own_sum) {
-        const int64_t per = (d.B + kFinSplit - 1) / kFinSplit;
+        const int64_t per = (d.n_slots + kFinSplit - 1) / kFinSplit;
         const int64_t c0 = split * per;
-        const int64_t c1 = (c0 + per) < d.B ? (c0 + per) : d.B;
+        const int64_t c1 = (c0 + per) < d.n_slots ? (c0 + per) : d.n_slots;
         const double *p = d.partial + pos;
 #pragma unroll 8
         for (int64_t c = c0; c < c1; ++c) {

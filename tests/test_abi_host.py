@@ -56,9 +56,10 @@ def expand(tasks, n, n_m, rows, field_rows):
     S, F = 64 * rows, 64 * field_rows
     keys = []
     for kind, a, b in tasks:
-        if kind == 0:
-            bi = np.arange(a * S, min(a * S + S, n_tri))
-            bj = np.arange(b * S, min(b * S + S, n_tri))
+        if kind in (0, 2):
+            T = S if kind == 0 else 64
+            bi = np.arange(a * T, min(a * T + T, n_tri))
+            bj = np.arange(b * T, min(b * T + T, n_tri))
             I, J = np.meshgrid(bi, bj, indexing="ij")
             I, J = I.ravel(), J.ravel()
             if a == b:
@@ -110,4 +111,31 @@ def test_launch_order_puts_field_tasks_first(n, n_m, rows):
     tasks = B.plan_tasks(n, n_m, rows, 1)
     kinds = tasks[:, 0] if len(tasks) else np.zeros(0)
     n_field = int((kinds == 1).sum())
-    assert (kinds[:n_field] == 1).all() and (kinds[n_field:] == 0).all()
+    n_whole = int((kinds == 0).sum())
+    assert (kinds[:n_field] == 1).all() and (kinds[n_field:n_field + n_whole] == 0).all()
+    assert (kinds[n_field + n_whole:] == 2).all()
+
+
+@pytest.mark.parametrize("n,rows", [(64 * 2 * 9, 2), (10000, 2), (64 * 4 * 12 + 5, 4), (64 * 2 * 3, 2)])
+def test_tail_split_tile_pairs(n, rows):
+    """The block pairs at the smallest nonzero fold offsets run as 64 x 64
+    tile pairs at the end of the launch: every block is the stationary block
+    of exactly one split pair per split offset and the streamed block of
+    exactly one, and every tile pair of a split block pair appears once."""
+    tasks = B.plan_tasks(n, n - 1, rows, 1)
+    split = tasks[tasks[:, 0] == 2]
+    blocks = -(-n // (64 * rows))
+    assert len(split) % (rows * rows * blocks) == 0 and len(split) > 0
+    D = len(split) // (rows * rows * blocks)
+    assert D <= (blocks - 1) // 2
+    bi, bj = split[:, 1] // rows, split[:, 2] // rows
+    off = (bj - bi) % blocks
+    assert set(off.tolist()) == set(range(1, D + 1))
+    for k in range(1, D + 1):
+        sel = off == k
+        assert np.array_equal(np.sort(np.unique(bi[sel])), np.arange(blocks))
+        tiles = split[sel][:, 1:]
+        assert len(np.unique(tiles[:, 0] * 10**6 + tiles[:, 1])) == len(tiles) == blocks * rows * rows
+    whole = tasks[tasks[:, 0] == 0]
+    woff = (whole[:, 2] - whole[:, 1]) % blocks
+    assert not np.isin(woff, np.arange(1, D + 1)).any()
