@@ -20,6 +20,7 @@ struct symba_ctx {
     // scratch
     int32_t *parent = nullptr;   // [max_n] union-find offsets, zero between calls
     int32_t *touched = nullptr;  // [max_n]
+    int32_t *blk_groups = nullptr;  // [max_n / kFinBodies + max_problems] groups per final-kernel body block
     int2 *pairs = nullptr;       // [max_pairs]
     int2 *sorted = nullptr;      // [max_pairs]
     int32_t *bcnt = nullptr;     // [max_n]
@@ -246,6 +247,8 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
     c->max_boxes = max_n / symba::kWave + 2 * (int64_t)kMaxProblems;
     bool ok = hipMalloc(&c->parent, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
+              hipMalloc(&c->blk_groups, sizeof(int32_t) * (max_n / symba::kFinBodies + kMaxProblems)) ==
+                  hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
               hipMalloc(&c->sorted, sizeof(int2) * max_pairs) == hipSuccess &&
               hipMalloc(&c->bcnt, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -288,6 +291,7 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipDeviceSynchronize();
     (void)hipFree(c->parent);
     (void)hipFree(c->touched);
+    (void)hipFree(c->blk_groups);
     (void)hipFree(c->pairs);
     (void)hipFree(c->sorted);
     (void)hipFree(c->bcnt);
@@ -357,6 +361,7 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.partial = c->partial;
     d.parent = c->parent;
     d.touched = c->touched;
+    d.blk_groups = c->blk_groups;
     d.pairs = c->pairs;
     d.pair_scratch_cap = c->max_pairs;
     d.sorted = c->sorted;
@@ -416,7 +421,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     }
     int rc = grow_partial(c, partial_total);
     if (rc != SYMBA_OK) return rc;
-    int64_t task_total = 0, fin_total = 0, body_off = 0, pair_off = 0, box_off = 0;
+    int64_t task_total = 0, fin_total = 0, body_off = 0, blk_off = 0, pair_off = 0, box_off = 0;
     int n_binned = 0;
     size_t partial_off = 0;
     const symba::LaunchCfg cfg{c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
@@ -432,6 +437,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.partial = c->partial + partial_off;
         d.parent = c->parent + body_off;
         d.touched = c->touched + body_off;
+        d.blk_groups = c->blk_groups + blk_off;
         const int64_t share = std::min<int64_t>(std::max<int64_t>(q.out.pair_cap, 0), c->max_pairs - pair_off);
         d.pairs = c->pairs + pair_off;
         d.sorted = c->sorted + pair_off;
@@ -448,6 +454,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         task_total += d.n_tasks;
         fin_total += symba::final_blocks(q.n, kScatterBlocksBatch);
         body_off += q.n;
+        blk_off += plans[s].n_blk;
         pair_off += share;
         partial_off += plans[s].partial_doubles;
         groups.back().p1 = s + 1;
@@ -596,6 +603,7 @@ int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t 
                                                  : 0);  // binning
     const int64_t per_pair = 2 * (int64_t)sizeof(int2);                                 // pair lists
     return (int64_t)(p.partial_doubles * sizeof(double)) + per_body * n + per_pair * pair_cap +
+           (int64_t)sizeof(int32_t) * p.n_blk +  // groups per final-kernel body block
            (int64_t)sizeof(Desc);
 }
 

@@ -17,9 +17,7 @@ constexpr int kBinTempInts = 2 * 2048 + 2 * 2048 + 2 * 2049;  // cell counts, fi
 
 // Per-problem device counters (zero between calls).
 constexpr int kCtrPairs = 0;   // flagged pairs found
-constexpr int kCtrSpare = 1;   // unused
-constexpr int kCtrGroups = 2;  // encounter groups (components with >= 2 bodies)
-constexpr int kCtrStatus = 3;  // status bits
+constexpr int kCtrStatus = 3;  // status bits (slots 1 and 2 are unused)
 constexpr int kCtrSlots = 4;
 
 // Context-wide statistics accumulated over calls (read by symba_read_stats).
@@ -69,6 +67,7 @@ struct Desc {
     double *partial;      // [n_slots][3][n_tri] per-slot partial sums
     int32_t *parent;      // [n] union-find forest as offsets to the parent (0 = root), zero between calls
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
+    int32_t *blk_groups;  // [n_blk] encounter groups rooted in each final-kernel body block
     int2 *pairs;          // [pair_scratch_cap] flagged pairs as found, (min, max)
     int64_t pair_scratch_cap;
     int2 *sorted;         // [pair_scratch_cap] flagged pairs grouped by bucket
