@@ -22,10 +22,9 @@ struct symba_ctx {
     int32_t *touched = nullptr;  // [max_n]
     int32_t *blk_groups = nullptr;  // [max_n / kFinBodies + max_problems] groups per final-kernel body block
     int2 *pairs = nullptr;       // [max_pairs]
-    int2 *sorted = nullptr;      // [max_pairs]
+    int4 *sorted = nullptr;      // [max_pairs]
     int32_t *bcnt = nullptr;     // [max_n]
     int32_t *bfill = nullptr;    // [max_n]
-    int32_t *bstart = nullptr;   // [max_n + max_problems]
     unsigned long long *ctr = nullptr;  // [kCtrSlots * max_problems]
     unsigned long long *stats = nullptr;  // [kStatSlots]
     int32_t *bin_key = nullptr, *bin_tmp = nullptr, *bin_idx = nullptr;  // [max_n] each
@@ -250,10 +249,9 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->blk_groups, sizeof(int32_t) * (max_n / symba::kFinBodies + kMaxProblems)) ==
                   hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
-              hipMalloc(&c->sorted, sizeof(int2) * max_pairs) == hipSuccess &&
+              hipMalloc(&c->sorted, sizeof(int4) * max_pairs) == hipSuccess &&
               hipMalloc(&c->bcnt, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->bfill, sizeof(int32_t) * max_n) == hipSuccess &&
-              hipMalloc(&c->bstart, sizeof(int32_t) * (max_n + kMaxProblems)) == hipSuccess &&
               hipMalloc(&c->ctr, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
               hipMalloc(&c->stats, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
               hipMalloc(&c->bin_key, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -296,7 +294,6 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->sorted);
     (void)hipFree(c->bcnt);
     (void)hipFree(c->bfill);
-    (void)hipFree(c->bstart);
     (void)hipFree(c->ctr);
     (void)hipFree(c->stats);
     (void)hipFree(c->bin_key);
@@ -367,7 +364,6 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.sorted = c->sorted;
     d.bcnt = c->bcnt;
     d.bfill = c->bfill;
-    d.bstart = c->bstart;
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
     d.stats = c->stats;
@@ -443,7 +439,6 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         d.sorted = c->sorted + pair_off;
         d.bcnt = c->bcnt + body_off;
         d.bfill = c->bfill + body_off;
-        d.bstart = c->bstart + body_off + s;
         d.nb = symba::bucket_count(q.n);
         d.pair_scratch_cap = share;
         d.ctr = c->ctr + symba::kCtrSlots * (int64_t)s;
@@ -534,7 +529,9 @@ int symba_read_stats(symba_ctx *c, int64_t *candidates, int64_t *flagged, int64_
         hipMemcpy(h, c->stats, sizeof h, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemset(c->stats, 0, sizeof h) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return SYMBA_EDEVICE;
-    if (candidates) *candidates = (int64_t)h[symba::kStatCandidates];
+    int64_t cand = 0;
+    for (int k = 0; k < symba::kStatCandLanes; ++k) cand += (int64_t)h[symba::kStatCandidates + k];
+    if (candidates) *candidates = cand;
     if (flagged) *flagged = (int64_t)h[symba::kStatFlagged];
     if (problems) *problems = (int64_t)h[symba::kStatCalls];
     return SYMBA_OK;
@@ -601,7 +598,7 @@ int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t 
                              (use_bin(c, n, n_m) ? 3 * (int64_t)sizeof(int32_t) + 8 * (int64_t)sizeof(double) +
                                                        symba::kBoxDoubles * (int64_t)sizeof(double) / symba::kWave
                                                  : 0);  // binning
-    const int64_t per_pair = 2 * (int64_t)sizeof(int2);                                 // pair lists
+    const int64_t per_pair = (int64_t)sizeof(int2) + (int64_t)sizeof(int4);            // pair lists
     return (int64_t)(p.partial_doubles * sizeof(double)) + per_body * n + per_pair * pair_cap +
            (int64_t)sizeof(int32_t) * p.n_blk +  // groups per final-kernel body block
            (int64_t)sizeof(Desc);

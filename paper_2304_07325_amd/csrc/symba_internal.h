@@ -21,10 +21,11 @@ constexpr int kCtrStatus = 3;  // status bits (slots 1 and 2 are unused)
 constexpr int kCtrSlots = 4;
 
 // Context-wide statistics accumulated over calls (read by symba_read_stats).
-constexpr int kStatCandidates = 0;  // pairs passed by the screen to the exact test
 constexpr int kStatFlagged = 1;     // pairs flagged by the exact test
 constexpr int kStatCalls = 2;       // problems evaluated
-constexpr int kStatSlots = 4;
+constexpr int kStatCandidates = 4;  // pairs passed by the screen to the exact test, spread over
+constexpr int kStatCandLanes = 64;  // this many counters (one atomic per drain would serialise on one)
+constexpr int kStatSlots = kStatCandidates + kStatCandLanes;
 
 // Per-problem view handed to the kernels: inputs, outputs, plan and scratch slices.
 struct Desc {
@@ -70,10 +71,9 @@ struct Desc {
     int32_t *blk_groups;  // [n_blk] encounter groups rooted in each final-kernel body block
     int2 *pairs;          // [pair_scratch_cap] flagged pairs as found, (min, max)
     int64_t pair_scratch_cap;
-    int2 *sorted;         // [pair_scratch_cap] flagged pairs grouped by bucket
+    int4 *sorted;         // [pair_scratch_cap] flagged pairs grouped by bucket, with the bucket's range
     int32_t *bcnt;        // [nb] flagged pairs per bucket, zero between calls
     int32_t *bfill;       // [nb] bucket fill counters, zero between calls
-    int32_t *bstart;      // [nb + 1] bucket starts in the canonical order
     int32_t nb;           // buckets: min(n, kMaxBuckets)
     unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
     unsigned long long *stats;  // [kStatSlots] context-wide statistics

@@ -253,7 +253,8 @@ __device__ __forceinline__ void test_and_group(const Desc &d, bool valid, int i,
 // revisits never queue padding of the triangle; a field task's padding past n
 // is rejected by the test's range check.
 __device__ __forceinline__ void drain(const Desc &d, const Queue &Q, int head, int count) {
-    if (lane() == 0) atomicAdd(d.stats + kStatCandidates, (unsigned long long)count);
+    if (lane() == 0)
+        atomicAdd(d.stats + kStatCandidates + (blockIdx.x & (kStatCandLanes - 1)), (unsigned long long)count);
     const bool mine = lane() < count;
     uint2 c = make_uint2(0u, 0u);
     if (mine) c = Q.q[(head + lane()) & Q.mask];
@@ -1163,6 +1164,15 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     const int col = tid % kFinBodies, split = tid / kFinBodies;
     const int64_t pos = lb * kFinBodies + col;  // position in the binned order
     const bool own_sum = pos < d.n && (pos < d.n_tri || d.n_rows == 0);
+    // the label's first loads are issued before the partial sums so that
+    // their round trip overlaps them
+    int64_t k = pos;
+    int off0 = 0, tch = 0;
+    if (split == 0 && pos < d.n) {
+        if (d.bidx) k = d.bidx[pos];  // the caller's index
+        off0 = uf_load(d.parent + k);
+        tch = d.touched[k];
+    }
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (own_sum) {
         const int64_t per = (d.n_slots + kFinSplit - 1) / kFinSplit;
@@ -1182,7 +1192,6 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     __syncthreads();
     bool nonfinite = false, root_of_group = false;
     if (split == 0 && pos < d.n) {
-        const int64_t k = d.bidx ? d.bidx[pos] : pos;  // the caller's index
         if (own_sum) {
             for (int s2 = 1; s2 < kFinSplit; ++s2) {
                 sx += part[s2][0][col];
@@ -1199,11 +1208,10 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
         }
         nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
         // group label = union-find root, the smallest index of the component
-        const int g = uf_find(d.parent, (int)k);
+        const int g = off0 == 0 ? (int)k : uf_find(d.parent, (int)k);
         d.group_id[k] = g;
-        const int touched = d.touched[k];
-        root_of_group = touched && g == (int)k;
-        if (touched) d.touched[k] = 0;
+        root_of_group = tch && g == (int)k;
+        if (tch) d.touched[k] = 0;
     }
     const int groups = __syncthreads_count(root_of_group);
     const int bad = __syncthreads_or(nonfinite);
@@ -1250,19 +1258,17 @@ __device__ __forceinline__ void scan_buckets(FinLds &F, const Desc &d) {
 }
 
 // Scatter block r of `blocks`: each stored pair to a free slot of its bucket
-// (order inside a bucket is arbitrary here and fixed by the closing kernel).
-// Block 0 also publishes the bucket starts.
+// (order inside a bucket is arbitrary here and fixed by the closing kernel),
+// stored with its bucket's range [start, end) of the canonical order.
 __device__ __forceinline__ void scatter_pairs(FinLds &F, const Desc &d, int r, int blocks) {
     const int64_t found = (int64_t)d.ctr[kCtrPairs];
     if (found > d.pair_scratch_cap) return;  // not every pair was stored: no order to produce
     scan_buckets(F, d);
-    if (r == 0)
-        for (int k = threadIdx.x; k <= d.nb; k += kFinalizeThreads) d.bstart[k] = F.scan[k];
     for (int64_t p = (int64_t)r * kFinalizeThreads + threadIdx.x; p < found; p += (int64_t)blocks * kFinalizeThreads) {
         const int2 e = d.pairs[p];
         const int bk = bucket_of(d, e.x);
         const int slot = F.scan[bk] + atomicAdd(d.bfill + bk, 1);
-        d.sorted[slot] = e;
+        d.sorted[slot] = make_int4(e.x, e.y, F.scan[bk], F.scan[bk + 1]);
     }
 }
 
@@ -1281,19 +1287,23 @@ __device__ __forceinline__ void final_block(FinLds &F, const Desc &d, int64_t fb
 // outputs (block 0).
 __device__ __forceinline__ void close_block(const Desc &d, int c, int blocks) {
     const int tid = threadIdx.x;
+    const int64_t s0 = (int64_t)c * kFinalizeThreads + tid;
+    // the first entry is read together with the pair count (a valid scratch
+    // address whether or not it holds a pair), saving a round trip
+    int4 first = make_int4(0, 0, 0, 0);
+    if (s0 < d.pair_scratch_cap) first = d.sorted[s0];
     const int64_t found = (int64_t)d.ctr[kCtrPairs];
     const int64_t cap = d.pair_cap < d.pair_scratch_cap ? d.pair_cap : d.pair_scratch_cap;
     const bool fits = found <= cap;
     const int64_t stride = (int64_t)blocks * kFinalizeThreads;
     if (found <= d.pair_scratch_cap) {
-        for (int64_t s = (int64_t)c * kFinalizeThreads + tid; s < found; s += stride) {
-            const int2 e = d.sorted[s];
-            const int bk = bucket_of(d, e.x);
-            const int b0 = d.bstart[bk], b1 = d.bstart[bk + 1];
+        for (int64_t s = s0; s < found; s += stride) {
+            const int4 e = s == s0 ? first : d.sorted[s];
+            const int b0 = e.z, b1 = e.w;
             const unsigned long long mine = ((unsigned long long)(unsigned)e.x << 32) | (unsigned)e.y;
             int less = 0;
             for (int q = b0; q < b1; ++q) {
-                const int2 o = d.sorted[q];
+                const int4 o = d.sorted[q];
                 less += (((unsigned long long)(unsigned)o.x << 32) | (unsigned)o.y) < mine;
             }
             if (fits) {

@@ -72,8 +72,10 @@ class Server:
         # pair scratch for any batch of at most max_batch_bodies bodies
         self.max_pairs = min(4 * self.max_batch_bodies + 4096 * 64, 2**31 - 1)
         self.ctx = B.Context(max_n=self.max_batch_bodies, max_pairs=self.max_pairs)
-        # the context's own scratch, sized by max_batch_bodies and max_pairs
-        self.fixed_bytes = 24 * self.max_batch_bodies + 16 * self.max_pairs + (1 << 20)
+        # the context's own scratch, sized by max_batch_bodies and max_pairs: per
+        # body the union-find, bucket and binning arrays (~96 B), per pair the
+        # found and the bucket-sorted lists (24 B), plus descriptors and counters
+        self.fixed_bytes = 96 * self.max_batch_bodies + 24 * self.max_pairs + (1 << 20)
         self.sims = []
         for (state, n_m), n in zip(sims, ns):
             self.sims.append(_Sim(state=state, n=n, n_m=int(n_m),
