@@ -101,6 +101,21 @@ int field_rows_for(int64_t n_field, int opt) {
 #define SYMBA_TAIL_SPLIT 2
 #endif
 
+// The split only pays when the launch is a few rounds of workgroups deep, so
+// that its ragged end is a sizeable part of the kernel; deeper launches keep
+// every block pair whole.  Rounds are counted against MI355X's 256 CUs at the
+// tile kernel's occupancy (6, 4, 2 workgroups per CU for 1, 2, 4 rows): a
+// fixed planning constant, so that the plan, and with it the summation order,
+// does not depend on the device.
+constexpr int64_t kPlanCUs = 256;
+constexpr int64_t kSplitMaxRounds = 6;
+
+int64_t tail_split(int64_t B, int rows) {
+    const int64_t slots = kPlanCUs * (rows == 1 ? 6 : rows == 2 ? 4 : 2);
+    if (symba::fold_count(B) >= kSplitMaxRounds * slots) return 0;
+    return symba::split_diagonals(B, rows, SYMBA_TAIL_SPLIT);
+}
+
 struct Plan {
     int64_t n_rows, n_tri, B, n_split, n_whole, n_slots, n_tri_tasks, n_field_tasks, n_blk;
     int rows;
@@ -116,7 +131,7 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
     p.rows = rows;
     if (p.n_rows > 0) {
         p.B = (p.n_tri + S - 1) / S;
-        p.n_split = symba::split_diagonals(p.B, rows, SYMBA_TAIL_SPLIT);
+        p.n_split = tail_split(p.B, rows);
         p.n_whole = symba::whole_count(p.B, p.n_split);
         p.n_tri_tasks = p.n_whole + p.n_split * p.B * rows * rows;
         p.n_slots = symba::partial_slots(p.B, rows, p.n_split);

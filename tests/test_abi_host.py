@@ -139,3 +139,14 @@ def test_tail_split_tile_pairs(n, rows):
     whole = tasks[tasks[:, 0] == 0]
     woff = (whole[:, 2] - whole[:, 1]) % blocks
     assert not np.isin(woff, np.arange(1, D + 1)).any()
+
+
+@pytest.mark.parametrize("n,rows", [(50000, 4), (30000, 2)])
+def test_deep_launches_keep_block_pairs_whole(n, rows):
+    """A triangle many workgroup rounds deep has no split block pairs: its
+    ragged end is a small part of the kernel, so the split would only add
+    per-task overhead."""
+    tasks = B.plan_tasks(n, n - 1, rows, 1)
+    assert (tasks[:, 0] != 2).all()
+    blocks = -(-n // (64 * rows))
+    assert len(tasks) == blocks * ((blocks - 1) // 2 + 1) + (blocks // 2 if blocks % 2 == 0 else 0)
