@@ -64,6 +64,8 @@ def test_tile_options(ctx, ora, rows, field_rows):
     ctx.set_option(B.OPT_FIELD_ROWS, field_rows)
     try:
         for n, n_m in ((777, 776), (1100, 300), (530, 530)):
+            if rows > 1 and n == 777:  # this case runs split block pairs (tile-pair tasks) at the end
+                assert (B.plan_tasks(n, n_m, rows, field_rows)[:, 0] == 2).any()
             s = G.dense_state(n, seed=7 * n + rows, box=3.0, n_m=n_m)
             compare(ctx, ora, s, n_m, label=f"rows={rows} field_rows={field_rows}")
     finally:
