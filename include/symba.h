@@ -62,7 +62,7 @@ extern "C" {
 /* Context options (symba_set_option). */
 #define SYMBA_OPT_TILE_ROWS 1   /* bodies per lane in triangle tiles: 1, 2 or 4 (0 = automatic) */
 #define SYMBA_OPT_FIELD_ROWS 2  /* field bodies per lane in massive x field tiles: 1 or 2 (0 = automatic) */
-#define SYMBA_OPT_SCREEN 4      /* 0 = FP64 reach screen, 1 = FP32 closest-approach pre-screen */
+#define SYMBA_OPT_SCREEN 4      /* pair screen: 0 = the conservative FP64 screen, the only value accepted */
 #define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
 #define SYMBA_OPT_BIN 6         /* spatial binning: 0 = by problem size, 1 = never, 2 = always */
 
@@ -119,8 +119,9 @@ int symba_ctx_create(symba_ctx **ctx, int device, int64_t max_n, int64_t max_pai
 int symba_ctx_destroy(symba_ctx *ctx);
 
 /* Set a tuning option (SYMBA_OPT_*).  Returns SYMBA_EINVAL for an unknown
- * option or value.  Options change speed only: results are unaffected, except
- * the FP32 pre-screen, which keeps the flags exact by an FP64 confirm. */
+ * option or value.  Options change speed only: pairs, groups and status are
+ * unaffected; the tile sizes change the order in which the accelerations are
+ * summed, so their bits (not their tolerance) depend on them. */
 int symba_set_option(symba_ctx *ctx, int option, int value);
 
 /* One kick/encounter evaluation (Sec. 2 of the paper): accelerations over the

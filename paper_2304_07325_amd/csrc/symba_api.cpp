@@ -347,7 +347,7 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             c->opt_timing = value;
             return SYMBA_OK;
         case SYMBA_OPT_SCREEN:
-            if (value != 0) return SYMBA_EINVAL;  // the FP32 pre-screen is not built yet
+            if (value != 0) return SYMBA_EINVAL;  // only the FP64 screen exists
             c->opt_screen = value;
             return SYMBA_OK;
         default:
@@ -382,7 +382,7 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
     d.stats = c->stats;
-    const symba::LaunchCfg cfg{c->opt_screen, kScatterBlocks, kCloseBlocks};
+    const symba::LaunchCfg cfg{kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
     const symba::TileGroup g{rows, field_rows, binned, 0, 1, 0, d.n_tasks};
@@ -435,7 +435,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     int64_t task_total = 0, fin_total = 0, body_off = 0, blk_off = 0, pair_off = 0, box_off = 0;
     int n_binned = 0;
     size_t partial_off = 0;
-    const symba::LaunchCfg cfg{c->opt_screen, kScatterBlocksBatch, kCloseBlocksBatch};
+    const symba::LaunchCfg cfg{kScatterBlocksBatch, kCloseBlocksBatch};
     for (int32_t s = 0; s < n_problems; ++s) {
         const int k = order[s];
         const symba_problem &q = probs[k];

@@ -100,7 +100,6 @@ struct TileGroup {
 };
 
 struct LaunchCfg {
-    int screen;      // 0 FP64 reach screen, 1 FP32 pre-screen
     int scatter_blocks_per_problem;  // pair-scatter blocks per problem (final kernel)
     int close_blocks_per_problem;    // closing-kernel blocks per problem
 };
