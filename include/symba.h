@@ -62,9 +62,16 @@ extern "C" {
 /* Context options (symba_set_option). */
 #define SYMBA_OPT_TILE_ROWS 1   /* bodies per lane in triangle tiles: 1, 2 or 4 (0 = automatic) */
 #define SYMBA_OPT_FIELD_ROWS 2  /* field bodies per lane in massive x field tiles: 1 or 2 (0 = automatic) */
-#define SYMBA_OPT_SCREEN 4      /* pair screen: 0 = the conservative FP64 screen, the only value accepted */
+#define SYMBA_OPT_SCREEN 4      /* pair screen precision: SYMBA_SCREEN_* below.  Both screens are
+                                   conservative and every candidate gets the exact FP64 test, so the
+                                   pair list, groups and accelerations are the same bits either way */
 #define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
 #define SYMBA_OPT_BIN 6         /* spatial binning: 0 = by problem size, 1 = never, 2 = always */
+
+/* Values of SYMBA_OPT_SCREEN. */
+#define SYMBA_SCREEN_AUTO 0  /* the library's choice: the FP32 screen */
+#define SYMBA_SCREEN_FP32 1  /* screen data rounded to FP32, margins proven to cover the rounding */
+#define SYMBA_SCREEN_FP64 2  /* the FP64 screen */
 
 typedef struct symba_ctx symba_ctx;
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libsymba.so")
 SYMBA_OK, SYMBA_EINVAL, SYMBA_ENOMEM, SYMBA_EDEVICE, SYMBA_ETOOBIG = 0, 1, 2, 3, 4
 STATUS_CAPACITY, STATUS_NONFINITE = 1, 2
 OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN = 1, 2, 4, 5, 6
+SCREEN_AUTO, SCREEN_FP32, SCREEN_FP64 = 0, 1, 2
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

@@ -154,6 +154,11 @@ bool use_bin(const symba_ctx *c, int64_t n, int64_t n_m) {
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The FP32 screen unless the FP64 one is asked for: on gfx950 it issues one
+// more operation per pair but reads half the LDS bytes per streamed body and
+// holds fewer registers, and measures slightly faster.
+int screen32(const symba_ctx *c) { return c->opt_screen == SYMBA_SCREEN_FP64 ? 0 : 1; }
+
 // Points the descriptor's tile-kernel inputs at the binned copies (scratch at
 // body offset body_off, tile boxes at box_off) or at the caller's inputs.
 // Returns 1 when the problem is binned.  The binning temporaries are shared:
@@ -343,11 +348,13 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             c->opt_bin = value;
             return SYMBA_OK;
         case SYMBA_OPT_TIMING:
-            if (value != 0 && value != 1) return SYMBA_EINVAL;
+            if (value != SYMBA_SCREEN_AUTO && value != SYMBA_SCREEN_FP32 && value != SYMBA_SCREEN_FP64)
+                return SYMBA_EINVAL;
             c->opt_timing = value;
             return SYMBA_OK;
         case SYMBA_OPT_SCREEN:
-            if (value != 0) return SYMBA_EINVAL;  // only the FP64 screen exists
+            if (value != SYMBA_SCREEN_AUTO && value != SYMBA_SCREEN_FP32 && value != SYMBA_SCREEN_FP64)
+                return SYMBA_EINVAL;
             c->opt_screen = value;
             return SYMBA_OK;
         default:
@@ -385,7 +392,7 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     const symba::LaunchCfg cfg{kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
-    const symba::TileGroup g{rows, field_rows, binned, 0, 1, 0, d.n_tasks};
+    const symba::TileGroup g{rows, field_rows, binned, screen32(c), 0, 1, 0, d.n_tasks};
     hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, binned, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
@@ -441,7 +448,7 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         const symba_problem &q = probs[k];
         if (groups.empty() || groups.back().rows != rows[k] || groups.back().field_rows != frows[k] ||
             groups.back().binned != bins[k])
-            groups.push_back(symba::TileGroup{rows[k], frows[k], bins[k], s, s, task_total, 0});
+            groups.push_back(symba::TileGroup{rows[k], frows[k], bins[k], screen32(c), s, s, task_total, 0});
         Desc &d = ds[s];
         fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[s], frows[k]);
         d.task_base = task_total;

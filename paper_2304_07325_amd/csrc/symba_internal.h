@@ -95,6 +95,7 @@ struct TileGroup {
     int rows;        // 1, 2 or 4
     int field_rows;  // 1 or 2
     int binned;      // 1: the problems are binned
+    int screen32;    // 1: the pair screen runs in FP32 (SYMBA_OPT_SCREEN 1)
     int p0, p1;
     int64_t task_begin, n_tasks;
 };

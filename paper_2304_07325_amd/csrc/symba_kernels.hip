@@ -143,6 +143,36 @@ __device__ __forceinline__ bool screen(double r2, double ux, double uy, double u
     return !(r2 >= thr);
 }
 
+// The same screen in single precision (SYMBA_SCREEN_FP32).  Each body's
+// screen data (u or v, and Q) is rounded to FP32 and packed two floats per
+// double: (x, y) of u or v in one, (z, Q) in the other.  Q is first inflated
+// by a further 2^-16 and raised to at least FLT_MIN.  Let A = Q_i + Q_j +
+// u_i . v_j be the FP64 screen's threshold in exact arithmetic (0 <= A <=
+// 2 (Q_i + Q_j), as |u_i . v_j| <= Q_i + Q_j).  Rounding the six inputs and
+// the four operations moves the computed threshold by at most about
+// 9 * 2^-24 (Q_i + Q_j), and rounding r2 to FP32 moves it by a relative
+// 2^-24, at most 2 * 2^-24 (Q_i + Q_j) where r2 is near A; the 2^-16
+// inflation adds 256 * 2^-24 (Q_i + Q_j).  So a pair rejected here has r2
+// >= A and is rejected by the FP64 screen as well: no false negatives.  A
+// body whose Q exceeds 2^100 (or is NaN) gets Q = NaN, which makes all its
+// pairs candidates, so no FP32 overflow can hide a pair; an r2 beyond the
+// FP32 range becomes +inf and is rejected correctly.
+constexpr double kScreenInflate32 = 1.0 + 0x1p-16;
+
+__device__ __forceinline__ double pack2(float a, float b) {
+    return __hiloint2double(__float_as_int(b), __float_as_int(a));
+}
+__device__ __forceinline__ float lo_of(double v) { return __int_as_float(__double2loint(v)); }
+__device__ __forceinline__ float hi_of(double v) { return __int_as_float(__double2hiint(v)); }
+
+__device__ __forceinline__ bool screen32(double r2, double uxy, double uzq, double vxy, double vzq) {
+    const float thr = __builtin_fmaf(lo_of(uzq), lo_of(vzq),
+                                     __builtin_fmaf(hi_of(uxy), hi_of(vxy),
+                                                    __builtin_fmaf(lo_of(uxy), lo_of(vxy),
+                                                                   hi_of(uzq) + hi_of(vzq))));
+    return !((float)r2 >= thr);
+}
+
 // The library's encounter test, operation for operation as documented in
 // symba.h; both orientations of a pair give the same bits.
 __device__ __forceinline__ bool encounter_test(double dx, double dy, double dz, double wx,
@@ -305,7 +335,7 @@ struct Body {
     double x, y, z, m, vx, vy, vz, Q;
 };
 
-template <bool REG>
+template <bool REG, bool F32>
 __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
     Body b;
     if (k < limit) {
@@ -326,16 +356,22 @@ __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limi
         b.x = kPadPos;
         b.y = b.z = b.m = b.vx = b.vy = b.vz = b.Q = 0.0;
     }
+    if constexpr (F32) {  // screen data as FP32, packed (see screen32)
+        const float Q = b.Q <= 0x1p100 ? fmaxf((float)(b.Q * kScreenInflate32), FLT_MIN) : __builtin_nanf("");
+        b.vx = pack2((float)b.vx, (float)b.vy);
+        b.vy = pack2((float)b.vz, Q);
+        b.vz = b.Q = 0.0;
+    }
     return b;
 }
 
 // Stage bodies [j0, j0 + 64 nq) (entries past `limit` become padding) into
 // tiles 0..nq-1 of the workgroup's LDS, each entry also at +64.  All threads
 // of the workgroup take part; the caller brackets it with barriers.
-template <int RS>
+template <int RS, bool F32>
 __device__ __forceinline__ void stage(const Desc &d, TaskLds<RS> &L, int64_t j0, int nq, int64_t limit) {
     for (int e = threadIdx.x; e < nq * kWave; e += kTaskThreads) {
-        const Body b = load_body<false>(d, j0 + e, limit);
+        const Body b = load_body<false, F32>(d, j0 + e, limit);
         const int q = e / kWave, jj = e % kWave;
         L.tile.xy[q][jj] = L.tile.xy[q][jj + kWave] = make_double2(b.x, b.y);
         L.tile.zm[q][jj] = L.tile.zm[q][jj + kWave] = make_double2(b.z, b.m);
@@ -344,11 +380,21 @@ __device__ __forceinline__ void stage(const Desc &d, TaskLds<RS> &L, int64_t j0,
     }
 }
 
-template <int RS>
+template <int RS, bool F32>
 __device__ __forceinline__ Body tile_body(const TaskLds<RS> &L, int q, int idx) {
-    const double2 a = L.tile.xy[q][idx], b = L.tile.zm[q][idx], c = L.tile.vxy[q][idx],
-                  e = L.tile.vzq[q][idx];
+    const double2 a = L.tile.xy[q][idx], b = L.tile.zm[q][idx], c = L.tile.vxy[q][idx];
+    if constexpr (F32) return Body{a.x, a.y, b.x, b.y, c.x, c.y, 0.0, 0.0};  // packed screen data
+    const double2 e = L.tile.vzq[q][idx];
     return Body{a.x, a.y, b.x, b.y, c.x, c.y, e.x, e.y};
+}
+
+// The screen of a pair from its register-side and LDS-side bodies.
+template <bool F32>
+__device__ __forceinline__ bool screen_pair(double r2, const Body &reg, const Body &lds) {
+    if constexpr (F32)
+        return screen32(r2, reg.vx, reg.vy, lds.vx, lds.vy);
+    else
+        return screen(r2, reg.vx, reg.vy, reg.vz, reg.Q, lds.vx, lds.vy, lds.vz, lds.Q);
 }
 
 // Position and mass of a tile entry (the screen-free loops read nothing else).
@@ -416,11 +462,11 @@ __device__ __forceinline__ void write_partial(const Desc &d, int64_t slot, int64
 // Screen of the pairs of step t (tile entry l + t) against the first NACT
 // slots, pushing the candidates.  Used to revisit the rare steps that had one;
 // it repeats the hot loop's screen operation for operation.
-template <int R, int RS, int NACT>
+template <int R, int RS, int NACT, bool F32>
 __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, int q, const Slots<R> &S,
                                           int64_t ib, int64_t js, int t, Queue &Q) {
     const int l = lane();
-    const Body J = tile_body(L, q, l + t);
+    const Body J = tile_body<RS, F32>(L, q, l + t);
     const int64_t j = js + ((l + t) & (kWave - 1));
 #pragma unroll
     for (int r = 0; r < NACT; ++r) {
@@ -430,7 +476,7 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
         // padding past n_tri (which may hold field bodies' positions) never
         // becomes a candidate, even next to a body with an infinite q
         const int64_t i = ib + r * kWave + l;
-        const bool c = i < d.n_tri && j < d.n_tri && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+        const bool c = i < d.n_tri && j < d.n_tri && screen_pair<F32>(r2, I, J);
         const unsigned long long mask = __ballot(c);
         if (mask) push(Q, mask, c, i, j);
     }
@@ -442,19 +488,19 @@ __device__ __forceinline__ void push_step(const Desc &d, const TaskLds<RS> &L, i
 // tile entry (l + t0) mod 64 and ends with those of entry (l + t0 + 16) mod 64.
 // Steps whose screen passed anywhere in the wave are only marked in a scalar
 // bit mask; the candidates are pushed afterwards (no branch in the loop).
-template <int R, int RS, int NACT, bool SCR>
+template <int R, int RS, int NACT, bool SCR, bool F32>
 __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> &L, int q, Slots<R> &S,
                                                int64_t ib, int64_t js, int t0, Queue &Q, double &ajx,
                                                double &ajy, double &ajz) {
     const int l = lane();
     ajx = ajy = ajz = 0.0;
     unsigned pending = 0;
-    Body Jn = SCR ? tile_body(L, q, l + t0) : tile_pos(L, q, l + t0);
+    Body Jn = SCR ? tile_body<RS, F32>(L, q, l + t0) : tile_pos(L, q, l + t0);
 #pragma unroll kRotUnroll
     for (int u = 0; u < kSteps; ++u) {
         const Body J = Jn;
         // one step ahead: the LDS latency hides behind this step
-        Jn = SCR ? tile_body(L, q, l + t0 + u + 1) : tile_pos(L, q, l + t0 + u + 1);
+        Jn = SCR ? tile_body<RS, F32>(L, q, l + t0 + u + 1) : tile_pos(L, q, l + t0 + u + 1);
         unsigned long long any = 0;
 #pragma unroll
         for (int r = 0; r < NACT; ++r) {
@@ -470,7 +516,7 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
             ajy = __builtin_fma(-fj, dy, ajy);
             ajz = __builtin_fma(-fj, dz, ajz);
             if (SCR)
-                any |= __builtin_amdgcn_ballot_w64(screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q));
+                any |= __builtin_amdgcn_ballot_w64(screen_pair<F32>(r2, I, J));
         }
         if (SCR) pending |= nonzero(any) << u;
         ajx = rotate_dpp(ajx);
@@ -480,7 +526,7 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
     while (pending) {
         const int u = __builtin_ctz(pending);
         pending &= pending - 1;
-        push_step<R, RS, NACT>(d, L, q, S, ib, js, t0 + u, Q);
+        push_step<R, RS, NACT, F32>(d, L, q, S, ib, js, t0 + u, Q);
     }
 }
 
@@ -488,13 +534,13 @@ __device__ __forceinline__ void rotation_range(const Desc &d, const TaskLds<RS> 
 // 1..63: each unordered pair is met from both ends, only the stationary side
 // is accumulated, and the pair is screened once (from the lane whose partner
 // is 1..31 steps ahead, or 32 steps ahead for the lower half of the wave).
-template <int R, int RS, int QS>
+template <int R, int RS, int QS, bool F32>
 __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> &L, Slots<R> &S,
                                                int64_t ib, int t0, Queue &Q) {
     const int l = lane();
     unsigned pending = 0;
     for (int t = (t0 > 0 ? t0 : 1); t < t0 + kSteps; ++t) {
-        const Body J = tile_body(L, QS, l + t);
+        const Body J = tile_body<RS, F32>(L, QS, l + t);
         const Body &I = S.b[QS];
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
@@ -503,37 +549,37 @@ __device__ __forceinline__ void diagonal_range(const Desc &d, const TaskLds<RS> 
         S.ay[QS] = __builtin_fma(fi, dy, S.ay[QS]);
         S.az[QS] = __builtin_fma(fi, dz, S.az[QS]);
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
-        const bool c = owner && screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+        const bool c = owner && screen_pair<F32>(r2, I, J);
         pending |= nonzero(__builtin_amdgcn_ballot_w64(c)) << (t - t0);
     }
     while (pending) {
         const int t = t0 + __builtin_ctz(pending);
         pending &= pending - 1;
-        const Body J = tile_body(L, QS, l + t);
+        const Body J = tile_body<RS, F32>(L, QS, l + t);
         const Body &I = S.b[QS];
         const double dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         const bool owner = (t < kWave / 2) || (t == kWave / 2 && l < kWave / 2);
         const int64_t i = ib + QS * kWave + l, j = ib + QS * kWave + ((l + t) & (kWave - 1));
         const bool c = owner && i < d.n_tri && j < d.n_tri &&
-                       screen(r2, I.vx, I.vy, I.vz, I.Q, J.vx, J.vy, J.vz, J.Q);
+                       screen_pair<F32>(r2, I, J);
         const unsigned long long mask = __ballot(c);
         if (mask) push(Q, mask, c, i, j);
         maybe_drain(d, Q);
     }
 }
 
-template <int R, int RS, int QS>
+template <int R, int RS, int QS, bool F32>
 __device__ __forceinline__ void diagonal_tiles(const Desc &d, const TaskLds<RS> &L, Slots<R> &S, int64_t ib,
                                                int t0, Queue &Q, double (&aj)[R][3]) {
     if constexpr (QS < R) {
         if constexpr (QS > 0)
-            rotation_range<R, RS, QS, true>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0], aj[QS][1],
+            rotation_range<R, RS, QS, true, F32>(d, L, QS, S, ib, ib + QS * kWave, t0, Q, aj[QS][0], aj[QS][1],
                                             aj[QS][2]);
         else
             aj[0][0] = aj[0][1] = aj[0][2] = 0.0;
-        diagonal_range<R, RS, QS>(d, L, S, ib, t0, Q);
-        diagonal_tiles<R, RS, QS + 1>(d, L, S, ib, t0, Q, aj);
+        diagonal_range<R, RS, QS, F32>(d, L, S, ib, t0, Q);
+        diagonal_tiles<R, RS, QS + 1, F32>(d, L, S, ib, t0, Q, aj);
     }
 }
 
@@ -582,7 +628,7 @@ __device__ __forceinline__ void write_sums(const Desc &d, TaskLds<RS> &L, const 
 // workgroup.  Partial sums land in slot J for the stationary bodies of block
 // I and in slot I for the bodies of block J (slot I for both when I == J).
 // BIN: the problem is binned, so tile pairs that cannot meet run screen-free.
-template <int R, int RS, bool BIN>
+template <int R, int RS, bool BIN, bool F32>
 __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t I,
                                               int64_t J) {
     const int l = lane(), w = wave_id();
@@ -591,7 +637,7 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
     Slots<R> S;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        S.b[r] = load_body<true>(d, ib + r * kWave + l, d.n_tri);
+        S.b[r] = load_body<true, F32>(d, ib + r * kWave + l, d.n_tri);
         S.ax[r] = S.ay[r] = S.az[r] = 0.0;
     }
     // lane r R + q decides stationary tile r against streamed tile q (the box
@@ -608,21 +654,21 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
             free_q |= (all ? 1u : 0u) << q;
         }
     }
-    stage(d, L, jb, R, d.n_tri);
+    stage<RS, F32>(d, L, jb, R, d.n_tri);
     __syncthreads();
     double aj[R][3];
     if (I != J) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (BIN && ((free_q >> q) & 1u))
-                rotation_range<R, RS, R, !BIN>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                rotation_range<R, RS, R, !BIN, F32>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
                                                aj[q][2]);
             else
-                rotation_range<R, RS, R, true>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                rotation_range<R, RS, R, true, F32>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
                                                aj[q][2]);
         }
     } else {
-        diagonal_tiles<R, RS, 0>(d, L, S, ib, t0, Q, aj);
+        diagonal_tiles<R, RS, 0, F32>(d, L, S, ib, t0, Q, aj);
     }
     __syncthreads();  // every wave is done with the tiles
     write_sums<R, RS, R>(d, L, S, aj, t0, I == J, J, ib, I, jb);
@@ -635,25 +681,25 @@ __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Que
 // Tile pair of a split diagonal (see split_decode): stationary tile r of
 // block I against streamed tile q of block J, both sides accumulated, by the
 // four waves of the workgroup as in a whole block pair.
-template <int R, int RS, bool BIN>
+template <int R, int RS, bool BIN, bool F32>
 __device__ __forceinline__ void split_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t s) {
     const int l = lane(), w = wave_id();
     const int t0 = w * kSteps;
     const SplitTask T = split_decode(d.B, R, s);
     const int64_t ib = (T.I * R + T.r) * kWave, jb = (T.J * R + T.q) * kWave;
     Slots<R> S;
-    S.b[0] = load_body<true>(d, ib + l, d.n_tri);
+    S.b[0] = load_body<true, F32>(d, ib + l, d.n_tri);
     S.ax[0] = S.ay[0] = S.az[0] = 0.0;
     bool apart = false;
     if (BIN) apart = __builtin_amdgcn_readfirstlane(
                          tiles_apart(d, tri_box(d, T.I * R + T.r), tri_box(d, T.J * R + T.q)) ? 1 : 0) != 0;
-    stage(d, L, jb, 1, d.n_tri);
+    stage<RS, F32>(d, L, jb, 1, d.n_tri);
     __syncthreads();
     double aj[R][3];
     if (BIN && apart)
-        rotation_range<R, RS, 1, !BIN>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+        rotation_range<R, RS, 1, !BIN, F32>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
     else
-        rotation_range<R, RS, 1, true>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+        rotation_range<R, RS, 1, true, F32>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
     __syncthreads();  // every wave is done with the tile
     write_sums<R, RS, 1>(d, L, S, aj, t0, false, T.slot_i, ib, T.slot_j, jb);
     drain_rest(d, Q);
@@ -662,7 +708,7 @@ __device__ __forceinline__ void split_task(const Desc &d, TaskLds<RS> &L, Queue 
 // This wave's 16 rows [t0, t0 + 16) of staged massive tile q against the
 // lane's field bodies (one-sided pairs); returns the bit mask of the steps
 // whose screen passed somewhere in the wave.
-template <int RF, int RS, bool SCR>
+template <int RF, int RS, bool SCR, bool F32>
 __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS> &L, int q, int64_t s0, int t0,
                                                 const Body (&fbody)[RF], double (&ax)[RF], double (&ay)[RF],
                                                 double (&az)[RF]) {
@@ -671,7 +717,7 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
         const int64_t row = s0 + q * kWave + t0 + u;
         if (row >= d.n_rows) break;
         // the same massive body in every lane
-        const Body I = SCR ? tile_body(L, q, t0 + u) : tile_pos(L, q, t0 + u);
+        const Body I = SCR ? tile_body<RS, F32>(L, q, t0 + u) : tile_pos(L, q, t0 + u);
         unsigned long long any = 0;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
@@ -683,7 +729,7 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
             ay[r] = __builtin_fma(-fj, dy, ay[r]);
             az[r] = __builtin_fma(-fj, dz, az[r]);
             if (SCR)
-                any |= __builtin_amdgcn_ballot_w64(screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q));
+                any |= __builtin_amdgcn_ballot_w64(screen_pair<F32>(r2, Fb, I));
         }
         if (SCR) pending |= nonzero(any) << u;
     }
@@ -693,7 +739,7 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
 // Field block fb against every massive row, by the four waves of the
 // workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
 // pairs; the field accelerations are complete at the end and written directly.
-template <int RF, int RS, bool BIN>
+template <int RF, int RS, bool BIN, bool F32>
 __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb) {
     const int l = lane(), w = wave_id();
     const int t0 = w * kSteps;
@@ -702,7 +748,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
     double ax[RF], ay[RF], az[RF];
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
-        fbody[r] = load_body<true>(d, f0 + r * kWave + l, d.n);
+        fbody[r] = load_body<true, F32>(d, f0 + r * kWave + l, d.n);
         ax[r] = ay[r] = az[r] = 0.0;
     }
     for (int64_t s0 = 0; s0 < d.n_rows; s0 += RS * kWave) {
@@ -721,23 +767,23 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
                 free_q |= (all ? 1u : 0u) << q;
             }
         }
-        stage(d, L, s0, nq, d.n_rows);
+        stage<RS, F32>(d, L, s0, nq, d.n_rows);
         __syncthreads();
         for (int q = 0; q < nq; ++q) {
             const bool apart = BIN && ((free_q >> q) & 1u);
-            unsigned pending = apart ? field_range<RF, RS, !BIN>(d, L, q, s0, t0, fbody, ax, ay, az)
-                                     : field_range<RF, RS, true>(d, L, q, s0, t0, fbody, ax, ay, az);
+            unsigned pending = apart ? field_range<RF, RS, !BIN, F32>(d, L, q, s0, t0, fbody, ax, ay, az)
+                                     : field_range<RF, RS, true, F32>(d, L, q, s0, t0, fbody, ax, ay, az);
             while (pending) {
                 const int u = __builtin_ctz(pending);
                 pending &= pending - 1;
                 const int64_t row = s0 + q * kWave + t0 + u;
-                const Body I = tile_body(L, q, t0 + u);
+                const Body I = tile_body<RS, F32>(L, q, t0 + u);
 #pragma unroll
                 for (int r = 0; r < RF; ++r) {
                     const Body &Fb = fbody[r];
                     const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
                     const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const bool c = screen(r2, Fb.vx, Fb.vy, Fb.vz, Fb.Q, I.vx, I.vy, I.vz, I.Q);
+                    const bool c = screen_pair<F32>(r2, Fb, I);
                     const unsigned long long mask = __ballot(c);
                     if (mask) push(Q, mask, c, row, f0 + r * kWave + l);
                 }
@@ -787,7 +833,7 @@ __device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, int
     return lo;
 }
 
-template <int R, int RF, bool BIN>
+template <int R, int RF, bool BIN, bool F32>
 __device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
     constexpr int RS = R > RF ? R : RF;
     // Without binning the tile kernel's inputs are the caller's arrays and no
@@ -807,28 +853,28 @@ __device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
     if (lt < d.n_whole) {
         int64_t I, J;
         whole_decode(d.B, d.n_split, lt, I, J);
-        triangle_task<R, RS, BIN>(d, L, Q, I, J);
+        triangle_task<R, RS, BIN, F32>(d, L, Q, I, J);
     } else if (lt < d.n_tri_tasks) {
-        split_task<R, RS, BIN>(d, L, Q, lt - d.n_whole);
+        split_task<R, RS, BIN, F32>(d, L, Q, lt - d.n_whole);
     } else {
-        field_task<RF, RS, BIN>(d, L, Q, lt - d.n_tri_tasks);
+        field_task<RF, RS, BIN, F32>(d, L, Q, lt - d.n_tri_tasks);
     }
 }
 
 // One problem: the descriptor is a kernel argument (scalar registers).
-template <int R, int RF, bool BIN>
+template <int R, int RF, bool BIN, bool F32>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles(const Desc d) {
-    run_task<R, RF, BIN>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
+    run_task<R, RF, BIN, F32>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
 }
 
 // Many problems of one tile size: every block finds its problem by the task
 // bases (descs is the group's slice of the launch's descriptors).
-template <int R, int RF, bool BIN>
+template <int R, int RF, bool BIN, bool F32>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles_batch(const Desc *__restrict__ descs, int n_desc, int64_t task_begin) {
     const int64_t t = task_begin + blockIdx.x;
-    run_task<R, RF, BIN>(descs[problem_of(descs, n_desc, t, 0)], t);
+    run_task<R, RF, BIN, F32>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1361,23 +1407,32 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_close_batch(const Desc *__
     close_block(descs[blockIdx.x / blocks], blockIdx.x % blocks, blocks);
 }
 
-template <int R, int RF, bool BIN>
+template <int R, int RF, bool BIN, bool F32>
 void launch_tiles(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
     if (descs)
-        hipLaunchKernelGGL((k_tiles_batch<R, RF, BIN>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream,
-                           descs + g.p0, g.p1 - g.p0, g.task_begin);
+        hipLaunchKernelGGL((k_tiles_batch<R, RF, BIN, F32>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0,
+                           stream, descs + g.p0, g.p1 - g.p0, g.task_begin);
     else
-        hipLaunchKernelGGL((k_tiles<R, RF, BIN>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream, one);
+        hipLaunchKernelGGL((k_tiles<R, RF, BIN, F32>), dim3((unsigned)g.n_tasks), dim3(kTaskThreads), 0, stream,
+                           one);
+}
+
+template <int R, int RF, bool BIN>
+void launch_tiles_s(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
+    if (g.screen32)
+        launch_tiles<R, RF, BIN, true>(g, one, descs, stream);
+    else
+        launch_tiles<R, RF, BIN, false>(g, one, descs, stream);
 }
 
 template <int R>
 void launch_tiles_r(const TileGroup &g, const Desc &one, const Desc *descs, hipStream_t stream) {
     if (g.field_rows == 2) {
-        if (g.binned) launch_tiles<R, 2, true>(g, one, descs, stream);
-        else launch_tiles<R, 2, false>(g, one, descs, stream);
+        if (g.binned) launch_tiles_s<R, 2, true>(g, one, descs, stream);
+        else launch_tiles_s<R, 2, false>(g, one, descs, stream);
     } else {
-        if (g.binned) launch_tiles<R, 1, true>(g, one, descs, stream);
-        else launch_tiles<R, 1, false>(g, one, descs, stream);
+        if (g.binned) launch_tiles_s<R, 1, true>(g, one, descs, stream);
+        else launch_tiles_s<R, 1, false>(g, one, descs, stream);
     }
 }
 

@@ -150,3 +150,13 @@ def test_deep_launches_keep_block_pairs_whole(n, rows):
     assert (tasks[:, 0] != 2).all()
     blocks = -(-n // (64 * rows))
     assert len(tasks) == blocks * ((blocks - 1) // 2 + 1) + (blocks // 2 if blocks % 2 == 0 else 0)
+
+
+def test_binding_constants_match_header():
+    """The binding's option and status constants are the header's values."""
+    import re
+    text = open(os.path.join(ROOT, "include", "symba.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SYMBA_(\w+)\s+(-?\d+)", text)}
+    for name in ("OPT_TILE_ROWS", "OPT_FIELD_ROWS", "OPT_SCREEN", "OPT_TIMING", "OPT_BIN",
+                 "SCREEN_AUTO", "SCREEN_FP32", "SCREEN_FP64"):
+        assert getattr(B, name) == defs[name], name
