@@ -197,6 +197,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
+        "screen": "f32 (conservative pair screen; every candidate gets the exact f64 test)",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: cold planetesimal disk (Sec. 3 recipe), N={n}, N_m={n_m}, "
                                f"dt=0.5 yr, rcrit=3 Hill radii, {evals} Kepler-advanced states resident in HBM",
