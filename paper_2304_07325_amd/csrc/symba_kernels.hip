@@ -2,14 +2,16 @@
 //
 // One step (the paper's Sec. 2: trapezoid pair loop, close-encounter check,
 // grouping of encounter pairs) runs as three launches:
-//   k_tiles  the folded trapezoid, one block pair per 4-wave workgroup: FP64
-//            pair forces into per-task partial sums, a conservative per-pair
-//            screen whose candidates are queued in LDS, and, after the task's
-//            last barrier, the exact FP64 encounter test of the candidates,
-//            flagged pairs appended, counted per index bucket and united in a
-//            lock-free union-find;
+//   k_tiles  the folded trapezoid, one block pair per 4-wave workgroup (in
+//            short launches the last block pairs cut into 64 x 64 tile
+//            pairs): FP64 pair forces into per-task partial sums, a
+//            conservative per-pair screen (FP32 or FP64) whose candidates are
+//            queued in LDS, and, after the task's last barrier, the exact FP64
+//            encounter test of the candidates, flagged pairs appended,
+//            counted per index bucket and united in a lock-free union-find;
 //   k_final  per body: fixed-order sum of the partial accelerations and the
-//            group label (union-find root); per pair: moved into its bucket;
+//            group label (union-find root), group roots counted per block;
+//            per pair: moved into its bucket;
 //   k_close  per pair: canonical (lexicographic) position by counting the
 //            smaller keys of its bucket, pair written out; scalar outputs;
 //            scratch returned to its between-calls state.
@@ -628,6 +630,7 @@ __device__ __forceinline__ void write_sums(const Desc &d, TaskLds<RS> &L, const 
 // workgroup.  Partial sums land in slot J for the stationary bodies of block
 // I and in slot I for the bodies of block J (slot I for both when I == J).
 // BIN: the problem is binned, so tile pairs that cannot meet run screen-free.
+// F32: the pair screen runs in FP32 (screen32).
 template <int R, int RS, bool BIN, bool F32>
 __device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t I,
                                               int64_t J) {
