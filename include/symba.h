@@ -108,6 +108,14 @@ typedef struct {
     int32_t *status;
 } symba_out;
 
+/* State of symba_step: positions and velocities are updated in place. */
+typedef struct {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    const double *m;
+    const double *rh;
+} symba_mstate;
+
 /* One independent problem of a batch. */
 typedef struct {
     symba_state state;
@@ -161,6 +169,26 @@ int symba_read_timing(symba_ctx *ctx, double *tiles_ms, double *finalize_ms, int
 
 /* Static text for a code. */
 const char *symba_strerror(int code);
+
+/* One step of length h of the democratic heliocentric map that SyMBA is
+ * built on (the paper's Sec. 1: Duncan, Levison & Lee 1998), outside close
+ * encounters: with heliocentric positions, barycentric velocities, G = 1 and
+ * the Sun's mass 1,
+ *   v += (h/2) a;  x += (h/2) P;  Kepler drift of every body about the Sun
+ *   for h;  x += (h/2) P;  a = the evaluation of symba_kick_encounter at the
+ *   new positions;  v += (h/2) a,
+ * P = sum of m v over the massive bodies (taken before and after the Kepler
+ * drift).  Every pair gets its full force: the partition-weighted kick of
+ * pairs inside the critical radius and the recursive sub-steps of encounter
+ * groups are not part of this step.
+ * s: positions and velocities, updated in place; out->ax/ay/az: on entry
+ * the accelerations at the current positions (from symba_kick_encounter or
+ * the previous step), on return those at the new positions, with the
+ * encounter pairs (screened |h| ahead), groups and status of the new state
+ * as symba_kick_encounter writes them.  h may be negative (the map is time
+ * reversible).  Errors and asynchrony as symba_kick_encounter. */
+int symba_step(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, double h,
+               double rcrit_factor, const symba_out *out, void *stream);
 
 /* Host-only helper (no device work): the task list of the folded trapezoid
  * for n, n_m and a tile size of 64*rows bodies, in the order a single call

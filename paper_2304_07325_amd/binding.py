@@ -35,6 +35,10 @@ class symba_out(ctypes.Structure):
                 ("status", _P)]
 
 
+class symba_mstate(ctypes.Structure):
+    _fields_ = [(k, _P) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rh")]
+
+
 class symba_problem(ctypes.Structure):
     _fields_ = [("state", symba_state), ("n", _I64), ("n_m", _I64), ("dt", _D),
                 ("rcrit_factor", _D), ("out", symba_out)]
@@ -42,7 +46,7 @@ class symba_problem(ctypes.Structure):
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
-           "symba_scratch_bytes", "symba_autotune", "symba_read_stats")
+           "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step")
 
 
 class SymbaError(RuntimeError):
@@ -63,6 +67,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.symba_kick_encounter.restype = ctypes.c_int
     lib.symba_kick_encounter.argtypes = [_P, ctypes.POINTER(symba_state), _I64, _I64, _D, _D,
                                          ctypes.POINTER(symba_out), _P]
+    lib.symba_step.restype = ctypes.c_int
+    lib.symba_step.argtypes = [_P, ctypes.POINTER(symba_mstate), _I64, _I64, _D, _D, ctypes.POINTER(symba_out), _P]
     lib.symba_kick_encounter_batch.restype = ctypes.c_int
     lib.symba_kick_encounter_batch.argtypes = [_P, ctypes.POINTER(symba_problem), ctypes.c_int32, _P]
     lib.symba_strerror.restype = ctypes.c_char_p
@@ -209,6 +215,19 @@ class Context:
         rc = lib().symba_kick_encounter(self._h, ctypes.byref(st), n, int(n_m), float(dt),
                                         float(rcrit_factor), ctypes.byref(o), _stream_handle(stream))
         _check(rc, "symba_kick_encounter")
+        return out
+
+    def step(self, state: dict, n_m: int, h: float, rcrit_factor: float, out: Outputs, stream=None) -> Outputs:
+        """symba_step: one step of length h in place on the device state; out holds
+        the accelerations at the current positions on entry and the new
+        evaluation on return."""
+        n = int(state["x"].numel())
+        _state_struct(state)  # the same checks as an evaluation's state
+        st = symba_mstate(*(state[k].data_ptr() for k in STATE_KEYS))
+        o = out.c_struct()
+        rc = lib().symba_step(self._h, ctypes.byref(st), n, int(n_m), float(h), float(rcrit_factor),
+                              ctypes.byref(o), _stream_handle(stream))
+        _check(rc, "symba_step")
         return out
 
     def autotune(self, state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs | None = None,

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsymba.so")
-SOURCES = [os.path.join(CSRC, "symba_kernels.hip"), os.path.join(CSRC, "symba_api.cpp")]
+SOURCES = [os.path.join(CSRC, "symba_kernels.hip"), os.path.join(CSRC, "symba_step.hip"),
+           os.path.join(CSRC, "symba_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -21,7 +22,7 @@ FLAGS = [
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1], "-o", LIB + ".tmp"]
+    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", *SOURCES, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

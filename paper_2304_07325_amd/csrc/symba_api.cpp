@@ -21,6 +21,7 @@ struct symba_ctx {
     int32_t *parent = nullptr;   // [max_n] union-find offsets, zero between calls
     int32_t *touched = nullptr;  // [max_n]
     int32_t *blk_groups = nullptr;  // [max_n / kFinBodies + max_problems] groups per final-kernel body block
+    double *mom = nullptr;          // [2][step_blocks(max_n)][3] momentum partial sums of symba_step
     int2 *pairs = nullptr;       // [max_pairs]
     int4 *sorted = nullptr;      // [max_pairs]
     int32_t *bcnt = nullptr;     // [max_n]
@@ -268,6 +269,7 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->blk_groups, sizeof(int32_t) * (max_n / symba::kFinBodies + kMaxProblems)) ==
                   hipSuccess &&
+              hipMalloc(&c->mom, sizeof(double) * 6 * symba::step_blocks(max_n)) == hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
               hipMalloc(&c->sorted, sizeof(int4) * max_pairs) == hipSuccess &&
               hipMalloc(&c->bcnt, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -310,6 +312,7 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->parent);
     (void)hipFree(c->touched);
     (void)hipFree(c->blk_groups);
+    (void)hipFree(c->mom);
     (void)hipFree(c->pairs);
     (void)hipFree(c->sorted);
     (void)hipFree(c->bcnt);
@@ -362,12 +365,13 @@ int symba_set_option(symba_ctx *c, int option, int value) {
     }
 }
 
-int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt,
-                         double rcrit_factor, const symba_out *out, void *stream) {
-    if (!c || bad_state(s) || bad_out(out)) return SYMBA_EINVAL;
-    if (n < 1 || n_m < 0 || n_m > n || bad_scalar(dt, rcrit_factor)) return SYMBA_EINVAL;
-    if (n > c->max_n) return SYMBA_ETOOBIG;
-    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+namespace {
+
+// One problem through the path (single-call launches); `kick`, when not
+// null, is the step's velocity arrays for the closing half kick of kick_h.
+int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt, double rcrit_factor,
+             const symba_out *out, void *stream, double *const *kick, double kick_h,
+             const symba::StepDesc *drifts) {
     const int n_tri_guess = (int)(n_m >= n - 1 ? n : n_m);
     const int rows = rows_for(c, n_tri_guess);
     const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
@@ -391,11 +395,52 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     d.stats = c->stats;
     const symba::LaunchCfg cfg{kScatterBlocks, kCloseBlocks};
     d.fin_base = 0;
+    if (kick) {
+        d.kvx = kick[0];
+        d.kvy = kick[1];
+        d.kvz = kick[2];
+        d.kick_h = kick_h;
+    }
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
     const symba::TileGroup g{rows, field_rows, binned, screen32(c), 0, 1, 0, d.n_tasks};
+    if (drifts && symba::launch_drifts(*drifts, (hipStream_t)stream) != hipSuccess) return SYMBA_EDEVICE;
     hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, binned, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
+}
+
+}  // namespace
+
+int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt,
+                         double rcrit_factor, const symba_out *out, void *stream) {
+    if (!c || bad_state(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || bad_scalar(dt, rcrit_factor)) return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    return evaluate(c, s, n, n_m, dt, rcrit_factor, out, stream, nullptr, 0.0, nullptr);
+}
+
+int symba_step(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double rcrit_factor,
+               const symba_out *out, void *stream) {
+    if (!c || !s || !s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m || !s->rh || bad_out(out))
+        return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || !std::isfinite(h) || bad_scalar(std::fabs(h), rcrit_factor))
+        return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    symba::StepDesc sd{};
+    sd.x = s->x; sd.y = s->y; sd.z = s->z; sd.vx = s->vx; sd.vy = s->vy; sd.vz = s->vz; sd.m = s->m;
+    sd.ax = out->ax; sd.ay = out->ay; sd.az = out->az;
+    sd.n = n;
+    sd.n_tri = n_m >= n - 1 ? n : n_m;
+    sd.kick_h = 0.5 * h;
+    sd.sun_h = 0.5 * h;
+    sd.kepler_h = h;
+    sd.mom0 = c->mom;
+    sd.mom1 = c->mom + 3 * symba::step_blocks(c->max_n);
+    const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
+    double *const kick[3] = {s->vx, s->vy, s->vz};
+    return evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, kick, 0.5 * h, &sd);
 }
 
 int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t n_problems,

@@ -87,7 +87,26 @@ struct Desc {
     int32_t *bin_hist;    // [2][2048] bodies per cell, zero between calls
     int32_t *bin_fill;    // [2][2048] cell fill counters, zero between calls
     int32_t *bin_start;   // [2][2049] cell starts
+    // step epilogue: v += kick_h a for every body once its acceleration is
+    // final (null outside symba_step)
+    double *kvx, *kvy, *kvz;
+    double kick_h;
 };
+
+// The drifts of a step (symba_step) before the evaluation at the new positions.
+struct StepDesc {
+    double *x, *y, *z, *vx, *vy, *vz;  // updated in place
+    const double *m;
+    const double *ax, *ay, *az;         // accelerations of the first kick
+    int64_t n, n_tri;                   // bodies; massive bodies [0, n_tri)
+    double kick_h, sun_h, kepler_h;     // h/2, h/2, h
+    double *mom0, *mom1;                // [step_blocks(n)][3] momentum partial sums
+};
+
+// Blocks of the drift kernels for n bodies, and their launch (first kick,
+// Sun drift, Kepler drift, Sun drift).
+int64_t step_blocks(int64_t n);
+hipError_t launch_drifts(const StepDesc &s, hipStream_t stream);
 
 // Problems [p0, p1) of a launch that share a tile size and binning: their tasks are
 // [task_begin, task_begin + n_tasks) of the launch's task numbering.

@@ -1255,6 +1255,11 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
             sy = d.ay[k];
             sz = d.az[k];
         }
+        if (d.kvx) {  // the step's closing half kick
+            d.kvx[k] += d.kick_h * sx;
+            d.kvy[k] += d.kick_h * sy;
+            d.kvz[k] += d.kick_h * sz;
+        }
         nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
         // group label = union-find root, the smallest index of the component
         const int g = off0 == 0 ? (int)k : uf_find(d.parent, (int)k);

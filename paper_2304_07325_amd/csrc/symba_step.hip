@@ -1,0 +1,198 @@
+// HIP kernels of the drifts around the kick/encounter evaluation: one step
+// of the democratic heliocentric map that SyMBA is built on (the paper's
+// Sec. 1: Duncan, Levison & Lee 1998, a variant of the Wisdom-Holman map),
+// outside close encounters.  With heliocentric positions x, barycentric
+// velocities v, G = 1 and the Sun's mass 1, a step of length h is
+//   kick(h/2) . Sun drift(h/2) . Kepler drift(h) . Sun drift(h/2) . kick(h/2):
+//   kick        v_i += (h/2) a_i, a_i the trapezoid's interaction acceleration;
+//   Sun drift   x_i += (h/2) P, P = sum over massive bodies of m_i v_i;
+//   Kepler      each body on its two-body orbit about the Sun for h.
+// Three launches do the first kick and the drifts (k_kick_momentum,
+// k_sun_kepler, k_sun); the evaluation at the new positions follows, and the
+// final kick is an epilogue of its final kernel.  P is summed in a fixed
+// order (per-block partial sums, then every block adds the partials in the
+// same order), so every block sees the same bits and the step is
+// reproducible.
+#include "symba_internal.h"
+
+#include <math.h>
+
+namespace symba {
+namespace {
+
+constexpr int kStepThreads = 256;
+constexpr int kStepWaves = kStepThreads / kWave;
+
+// Fixed-order block sum of one value per thread (shuffle tree in each wave,
+// then the waves in order); every thread gets the total.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < kStepWaves; ++k) t += lds[k];
+    return t;
+}
+
+// This block's share of P = sum m_i v_i over the massive bodies [0, n_tri).
+__device__ __forceinline__ void write_momentum(const StepDesc &s, double *part, int64_t k, double vx, double vy,
+                                               double vz) {
+    __shared__ double red[kStepWaves];
+    const double m = k < s.n_tri ? s.m[k] : 0.0;
+    const double px = block_sum(m * vx, red);
+    const double py = block_sum(m * vy, red);
+    const double pz = block_sum(m * vz, red);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = px;
+        part[3 * blockIdx.x + 1] = py;
+        part[3 * blockIdx.x + 2] = pz;
+    }
+}
+
+// P from the blocks' partial sums, in the same order in every block.
+__device__ __forceinline__ void read_momentum(const double *part, int nblk, double &px, double &py, double &pz) {
+    __shared__ double red[kStepWaves];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kStepThreads) {
+        a += part[3 * k];
+        b += part[3 * k + 1];
+        c += part[3 * k + 2];
+    }
+    px = block_sum(a, red);
+    py = block_sum(b, red);
+    pz = block_sum(c, red);
+}
+
+// Stumpff functions c0..c3 of x (Danby, Fundamentals of Celestial Mechanics,
+// Sec. 6.9): c0 = cos sqrt x, c1 = sin sqrt x / sqrt x, c2 = (1 - cos sqrt x) / x,
+// c3 = (sqrt x - sin sqrt x) / sqrt(x)^3, continued through x <= 0.  Near 0
+// the series of c2 and c3 (terms (-x)^k / (2k+2)! and (-x)^k / (2k+3)!),
+// then c0 = 1 - x c2 and c1 = 1 - x c3.
+__device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double &c2, double &c3) {
+    if (fabs(x) < 1.0) {
+        double t2 = 1.0 / 2.0, t3 = 1.0 / 6.0, s2 = t2, s3 = t3;
+        for (int k = 1; k <= 12; ++k) {
+            t2 *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+            t3 *= -x / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+            s2 += t2;
+            s3 += t3;
+        }
+        c2 = s2;
+        c3 = s3;
+        c0 = 1.0 - x * c2;
+        c1 = 1.0 - x * c3;
+    } else if (x > 0.0) {
+        const double q = sqrt(x), sn = sin(q), cs = cos(q);
+        c0 = cs;
+        c1 = sn / q;
+        c2 = (1.0 - cs) / x;
+        c3 = (q - sn) / (x * q);
+    } else {
+        const double q = sqrt(-x), sn = sinh(q), cs = cosh(q);
+        c0 = cs;
+        c1 = sn / q;
+        c2 = (cs - 1.0) / -x;
+        c3 = (sn - q) / (-x * q);
+    }
+}
+
+// Two-body drift about a centre of gravitational parameter 1 for time h, in
+// Danby's universal variable s: r0 s c1 + eta s^2 c2 + s^3 c3 = h with
+// beta = 2 / r0 - |v|^2, eta = x . v and the c's at beta s^2, solved by the
+// Laguerre-Conway iteration (Conway 1986), then the f and g functions
+// f = 1 - s^2 c2 / r0, g = h - s^3 c3, fdot = -s c1 / (r r0), gdot = 1 - s^2 c2 / r.
+__device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, double &vx, double &vy, double &vz,
+                                             double h) {
+    const double r0 = sqrt(x * x + y * y + z * z);
+    const double beta = 2.0 / r0 - (vx * vx + vy * vy + vz * vz);
+    const double eta = x * vx + y * vy + z * vz;
+    const double zeta = 1.0 - beta * r0;
+    double s = h / r0, c0, c1, c2, c3;
+    for (int it = 0; it < 40; ++it) {
+        stumpff(beta * s * s, c0, c1, c2, c3);
+        const double F = s * (r0 * c1 + s * (eta * c2 + s * c3)) - h;
+        const double dF = r0 * c0 + s * (eta * c1 + s * c2);
+        const double ddF = eta * c0 + zeta * s * c1;
+        const double root = sqrt(fabs(16.0 * dF * dF - 20.0 * F * ddF));
+        const double ds = -5.0 * F / (dF + (dF >= 0.0 ? root : -root));
+        s += ds;
+        if (!(fabs(ds) > 1e-15 * fabs(s))) break;  // converged (or NaN input)
+    }
+    stumpff(beta * s * s, c0, c1, c2, c3);
+    const double r = r0 * c0 + s * (eta * c1 + s * c2);
+    const double f = 1.0 - s * s * c2 / r0, g = h - s * s * s * c3;
+    const double fd = -s * c1 / (r * r0), gd = 1.0 - s * s * c2 / r;
+    const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
+    vx = fd * x + gd * vx;
+    vy = fd * y + gd * vy;
+    vz = fd * z + gd * vz;
+    x = nx;
+    y = ny;
+    z = nz;
+}
+
+// v += kick_h a, then this block's momentum partial sum.
+__global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc s) {
+    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (k < s.n) {
+        vx = s.vx[k] + s.kick_h * s.ax[k];
+        vy = s.vy[k] + s.kick_h * s.ay[k];
+        vz = s.vz[k] + s.kick_h * s.az[k];
+        s.vx[k] = vx;
+        s.vy[k] = vy;
+        s.vz[k] = vz;
+    }
+    write_momentum(s, s.mom0, k, vx, vy, vz);
+}
+
+// x += sun_h P, Kepler drift for kepler_h, then the new momentum partial sum.
+__global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc s) {
+    double px, py, pz;
+    read_momentum(s.mom0, (int)gridDim.x, px, py, pz);
+    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (k < s.n) {
+        double x = s.x[k] + s.sun_h * px, y = s.y[k] + s.sun_h * py, z = s.z[k] + s.sun_h * pz;
+        vx = s.vx[k];
+        vy = s.vy[k];
+        vz = s.vz[k];
+        kepler_drift(x, y, z, vx, vy, vz, s.kepler_h);
+        s.x[k] = x;
+        s.y[k] = y;
+        s.z[k] = z;
+        s.vx[k] = vx;
+        s.vy[k] = vy;
+        s.vz[k] = vz;
+    }
+    write_momentum(s, s.mom1, k, vx, vy, vz);
+}
+
+// x += sun_h P with the momentum after the Kepler drift.
+__global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc s) {
+    double px, py, pz;
+    read_momentum(s.mom1, (int)gridDim.x, px, py, pz);
+    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+    if (k < s.n) {
+        s.x[k] += s.sun_h * px;
+        s.y[k] += s.sun_h * py;
+        s.z[k] += s.sun_h * pz;
+    }
+}
+
+}  // namespace
+
+int64_t step_blocks(int64_t n) { return (n + kStepThreads - 1) / kStepThreads; }
+
+hipError_t launch_drifts(const StepDesc &s, hipStream_t stream) {
+    const unsigned blocks = (unsigned)step_blocks(s.n);
+    hipLaunchKernelGGL(k_kick_momentum, dim3(blocks), dim3(kStepThreads), 0, stream, s);
+    hipLaunchKernelGGL(k_sun_kepler, dim3(blocks), dim3(kStepThreads), 0, stream, s);
+    hipLaunchKernelGGL(k_sun, dim3(blocks), dim3(kStepThreads), 0, stream, s);
+    return hipGetLastError();
+}
+
+}  // namespace symba
