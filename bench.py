@@ -65,10 +65,39 @@ def traffic_from_profiles(n_tasks_per_launch_bytes=None):
     return t.get("hbm_bytes_per_launch")
 
 
+HOT_CHECK = {}   # a GPU evaluation of the 50k hot disk, checked against the oracle in the CPU leg
+
+
+def hot_oracle_check(o, c):
+    """The kept 50k hot-disk evaluation against the oracle: every pair and
+    label, 600 sampled accelerations."""
+    import numpy as np
+    g, n, n_m = c["gpu"], c["n"], c["n_m"]
+    pi, pj = o.pairs(c["state"], n_m, c["dt"], c["f"])
+    gid, ng = o.groups(n, pi, pj)
+    same_len = len(pi) == len(g["pair_i"])
+    mism = int(len(pi) != len(g["pair_i"])) if not same_len else int(
+        np.count_nonzero((pi != g["pair_i"]) | (pj != g["pair_j"])))
+    missed = len(set(zip(pi.tolist(), pj.tolist())) - set(zip(g["pair_i"].tolist(), g["pair_j"].tolist())))
+    rng = np.random.default_rng(5)
+    idx = rng.choice(n, 600, replace=False)
+    ref = np.stack([o.accel_body(c["state"], n_m, int(b)) for b in idx])
+    rel = np.linalg.norm(g["acc"][idx] - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    return dict(state=c["state_index"], pairs=len(pi), pair_mismatches=mism, false_negatives=missed,
+                label_mismatches=int(np.count_nonzero(gid != g["group_id"])), groups=ng, groups_gpu=g["n_groups"],
+                acc_rel_err=dict(sampled=len(idx), max=float(rel.max()), p99=float(np.percentile(rel, 99)),
+                                 median=float(np.median(rel))))
+
+
 def cpu_baseline(disk, n_m, dt, f, budget_s=15.0):
+    """The CPU leg: the oracle timed on a bounded sample of the headline
+    workload, and the oracle check of the kept 50k hot-disk evaluation."""
     import oracle
     from paper_2304_07325_amd import diskgen as dg
     o = oracle.default()
+    if HOT_CHECK:
+        HOT_CHECK["row"]["oracle_check"] = chk = hot_oracle_check(o, HOT_CHECK)
+        log(f"hot50k oracle check {chk}")
     pairs = dg.pair_count(disk.n, n_m)
     done, t0 = 0, time.perf_counter()
     while True:
@@ -94,6 +123,9 @@ def main():
     ap.add_argument("--workload", default="disk10k")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-others", action="store_true", help="skip the 1k, 100k-field and 50k-hot disks")
+    ap.add_argument("--no-step", action="store_true", help="skip the full-step (drifts + evaluation) legs")
+    ap.add_argument("--accuracy-years", type=float, default=1e4,
+                    help="length of the accuracy-disk integration of the step leg")
     ap.add_argument("--no-hot-check", action="store_true",
                     help="skip the oracle check of one 50k hot-disk evaluation (about 20 s of host time)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -184,6 +216,9 @@ def main():
     others = None
     if not args.no_others:
         others = bench_other_workloads(args, B, dg, torch)
+    step = None
+    if not args.no_step:
+        step = bench_step(args, B, dg, torch)
 
     result = {
         "metric": "FP64 pair-interactions/s (10k disk) + p50/p99 step latency, batched vs plain",
@@ -209,12 +244,98 @@ def main():
         "batched": batched,
         "served": served,
         "other_workloads": others,
+        "step": step,
     }
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(disk, n_m, dt, f)
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def bench_step(args, B, dg, torch):
+    """symba_step, the non-encounter step around the path: steps/s on the 10k
+    disk, and the paper's accuracy test (Sec. 3: 100 equal planetesimals 5
+    Hill radii apart, 0.1-year steps, 1e4 years) with its relative energy and
+    angular-momentum errors.  Every pair gets its full force (no encounter
+    sub-steps), so the steps with flagged encounter pairs are counted too."""
+    import numpy as np
+    f = dg.RCRIT_FACTOR
+    res = {}
+    w = dg.WORKLOADS[args.workload]
+    n, n_m = w["n"], w["n_massive"]
+    disk = dg.make_disk(n, n_m, w["kind"], w["seed"])
+    st = B.to_device_state(disk.state(0))
+    ctx = B.Context(max_n=n, max_pairs=max(16 * n, 1 << 16))
+    out = B.Outputs(n, max(16 * n, 1 << 16))
+    h = dg.DT_HALF_YEAR
+    ctx.kick_encounter(st, n_m, h, f, out=out)
+    for _ in range(5):
+        ctx.step(st, n_m, h, f, out)
+    torch.cuda.synchronize()
+    steps = 100
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(st, n_m, h, f, out)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    res[args.workload] = {"steps_per_s": 1.0 / sec, "ms_per_step": sec * 1e3,
+                          "pairs_per_s": dg.pair_count(n, n_m) / sec, "steps": steps}
+    log(f"step {args.workload}: {1.0 / sec:.0f} steps/s, {sec * 1e3:.4f} ms/step")
+    ctx.close()
+    # the accuracy test
+    acc_disk = dg.make_accuracy_disk(n=100)
+    s0 = acc_disk.state(0)
+    nm, h = acc_disk.n_massive, acc_disk.dt
+    total = int(round(args.accuracy_years * dg.YEAR / h))
+    st = B.to_device_state(s0)
+    ctx = B.Context(max_n=128, max_pairs=1 << 14)
+    out = B.Outputs(100, 1 << 13)
+    ctx.kick_encounter(st, nm, h, f, out=out)
+    torch.cuda.synchronize()
+    ctx.read_stats()
+
+    def invariants(s):
+        """Energy of the split Hamiltonian (Kepler + Sun + interaction terms,
+        heliocentric positions, barycentric velocities) and angular momentum."""
+        x = np.stack([s["x"], s["y"], s["z"]], 1)
+        v = np.stack([s["vx"], s["vy"], s["vz"]], 1)
+        m = s["m"]
+        p = (m[:, None] * v).sum(0)
+        e = float(np.sum(0.5 * m * np.sum(v * v, 1) - m / np.linalg.norm(x, axis=1)) + 0.5 * p @ p)
+        d = x[:, None, :] - x[None, :, :]
+        r = np.sqrt(np.sum(d * d, -1))
+        iu = np.triu_indices(len(m), 1)
+        e -= float(np.sum((m[:, None] * m[None, :])[iu] / r[iu]))
+        L = (m[:, None] * np.cross(x, v)).sum(0)
+        return e, L
+
+    e0, L0 = invariants(s0)
+    chunks, worst_e, worst_l = 50, 0.0, 0.0
+    per = max(total // chunks, 1)
+    t0 = time.perf_counter()
+    done = 0
+    while done < total:
+        k = min(per, total - done)
+        for _ in range(k):
+            ctx.step(st, nm, h, f, out)
+        done += k
+        torch.cuda.synchronize()
+        cur = {key: v.cpu().numpy() for key, v in st.items()}
+        e, L = invariants(cur)
+        worst_e = max(worst_e, abs(e - e0) / abs(e0))
+        worst_l = max(worst_l, float(np.linalg.norm(L - L0) / np.linalg.norm(L0)))
+    wall = time.perf_counter() - t0
+    _, flagged, calls = ctx.read_stats()
+    res["accuracy_disk"] = {"n": 100, "step_years": h / dg.YEAR, "years": done * h / dg.YEAR, "steps": done,
+                            "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
+                            "angmom_rel_err_max": worst_l, "checkpoints": chunks,
+                            "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
+                            "steps_per_s": done / wall}
+    log(f"accuracy disk: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s, energy err max "
+        f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}")
+    ctx.close()
+    return res
 
 
 def bench_other_workloads(args, B, dg, torch):
@@ -256,33 +377,15 @@ def bench_other_workloads(args, B, dg, torch):
                              pass_rate=cands / max(probs, 1) / pairs,
                              confirmed_fraction=flagged / cands if cands else None))
         if name == "hot50k" and not args.no_hot_check:
-            import oracle
-            ora = oracle.default()
+            # one evaluation kept for the CPU leg, which checks it against the oracle
             k = 3
             ctx.kick_encounter(states[k], n_m, dt, f, out=out)
             torch.cuda.synchronize()
-            g = out.to_host()
-            pi, pj = ora.pairs(host[k], n_m, dt, f)
-            gid, ng = ora.groups(n, pi, pj)
-            same_len = len(pi) == len(g["pair_i"])
-            mism = int(len(pi) != len(g["pair_i"])) if not same_len else int(
-                np.count_nonzero((pi != g["pair_i"]) | (pj != g["pair_j"])))
-            missed = len(set(zip(pi.tolist(), pj.tolist())) - set(zip(g["pair_i"].tolist(), g["pair_j"].tolist())))
-            rng = np.random.default_rng(5)
-            idx = rng.choice(n, 600, replace=False)
-            ref = np.stack([ora.accel_body(host[k], n_m, int(b)) for b in idx])
-            rel = np.linalg.norm(g["acc"][idx] - ref, axis=1) / np.linalg.norm(ref, axis=1)
-            r["oracle_check"] = dict(state=k, pairs=len(pi), pair_mismatches=mism, false_negatives=missed,
-                                     label_mismatches=int(np.count_nonzero(gid != g["group_id"])),
-                                     groups=ng, groups_gpu=g["n_groups"],
-                                     acc_rel_err=dict(sampled=len(idx), max=float(rel.max()),
-                                                      p99=float(np.percentile(rel, 99)),
-                                                      median=float(np.median(rel))))
+            HOT_CHECK.update(state_index=k, state=host[k], n=n, n_m=n_m, dt=dt, f=f, gpu=out.to_host(), row=r)
         ctx.close()
         res[name] = r
         log(f"{name}: {r['pairs_per_s']:.3e} pairs/s, {r['ms_per_step']:.3f} ms/step, "
-            f"screen pass rate {r['screen']['pass_rate']:.2e}" +
-            (f", oracle check {r['oracle_check']}" if "oracle_check" in r else ""))
+            f"screen pass rate {r['screen']['pass_rate']:.2e}")
     return res
 
 
