@@ -23,7 +23,7 @@ def ora():
 class Runner:
     """A device state with its outputs, stepped by symba_step."""
 
-    def __init__(self, s, n_m, h, screen=None):
+    def __init__(self, s, n_m, h, screen=None, binned=False):
         import torch
         from paper_2304_07325_amd import binding as B
         self.B, self.torch = B, torch
@@ -31,6 +31,8 @@ class Runner:
         self.ctx = B.Context(max_n=max(self.n, 64), max_pairs=1 << 16)
         if screen is not None:
             self.ctx.set_option(B.OPT_SCREEN, screen)
+        if binned:   # the evaluation in the binned order, whose final kick maps positions back
+            self.ctx.set_option(B.OPT_BIN, 2)
         self.st = B.to_device_state(s)
         self.out = B.Outputs(self.n, 1 << 15)
         self.ctx.kick_encounter(self.st, n_m, abs(h), F, out=self.out)
@@ -56,8 +58,9 @@ def _compare_state(got, want, tol):
         assert _rel(got[k], want[k]) < tol, (k, _rel(got[k], want[k]))
 
 
+@pytest.mark.parametrize("binned", [False, True])
 @pytest.mark.parametrize("which", ["disk1k", "dense_field"])
-def test_one_step_matches_oracle(ora, which):
+def test_one_step_matches_oracle(ora, which, binned):
     if which == "disk1k":
         w = dg.WORKLOADS["disk1k"]
         s = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"]).state(0)
@@ -65,8 +68,8 @@ def test_one_step_matches_oracle(ora, which):
     else:   # massive and field bodies on bound orbits, closer together
         d = dg.make_disk(900, 300, "hot", 77)
         s, n_m, h = d.state(0), 300, 0.1 * dg.YEAR
-    G.say("step", which)
-    r = Runner(s, n_m, h)
+    G.say("step", which, "binned" if binned else "")
+    r = Runner(s, n_m, h, binned=binned)
     r.step()
     got = r.state()
     want, acc_want = S.step(s, n_m, h, ora=ora)
