@@ -18,9 +18,9 @@ recursive sub-steps of encounter groups are not computed (their weighting
 function is not given).
 
 Plain float64 numpy, slow and direct: the Kepler drift solves the universal
-Kepler equation for the universal anomaly chi by Newton's method to full
-convergence (Curtis, Orbital Mechanics for Engineering Students, Sec. 3.7)
-and applies the Lagrange f and g coefficients.
+Kepler equation for the universal anomaly chi (Curtis, Orbital Mechanics for
+Engineering Students, Sec. 3.7) by bracketed Newton iterations to full
+convergence and applies the Lagrange f and g coefficients.
 """
 from __future__ import annotations
 
@@ -59,9 +59,26 @@ def stumpff_s(z):
     return out
 
 
-def kepler_drift(x, v, h, mu=1.0, max_iter=200):
+def _universal_f(chi, r0, vr0, alpha, smu, h):
+    """Curtis' universal Kepler equation F(chi) and F'(chi) = r (> 0, so F rises
+    monotonically from -inf to +inf); overflow of the hyperbolic functions is
+    mapped to the sign the monotone F must have there."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        z = alpha * chi * chi
+        C, S = stumpff_c(z), stumpff_s(z)
+        F = r0 * vr0 / smu * chi * chi * C + (1 - alpha * r0) * chi ** 3 * S + r0 * chi - smu * h
+        dF = r0 * vr0 / smu * chi * (1 - z * S) + (1 - alpha * r0) * chi * chi * C + r0
+    bad = ~np.isfinite(F)
+    F = np.where(bad, np.where(chi > 0, np.inf, -np.inf), F)
+    return F, dF
+
+
+def kepler_drift(x, v, h, mu=1.0, max_iter=400):
     """Each row of x, v (shape [n, 3]) moved along its two-body orbit about a
-    fixed centre of gravitational parameter mu for a time h."""
+    fixed centre of gravitational parameter mu for a time h.  The universal
+    anomaly is found by Newton's method kept inside a bracket of the root
+    (bisection whenever a Newton step would leave it), which converges for
+    every conic and arc length."""
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
     r0 = np.sqrt(np.sum(x * x, axis=1))
@@ -69,16 +86,39 @@ def kepler_drift(x, v, h, mu=1.0, max_iter=200):
     vr0 = np.sum(x * v, axis=1) / r0
     alpha = 2.0 / r0 - v0sq / mu                  # reciprocal semimajor axis
     smu = np.sqrt(mu)
-    chi = smu * np.abs(alpha) * h                 # initial guess (exact for a circle)
-    chi = np.where(alpha > 0, chi, smu * h / r0)
+    h = np.full(len(x), float(h)) if np.ndim(h) == 0 else np.asarray(h, dtype=np.float64)
+    # bracket [lo, hi] with F(lo) <= 0 <= F(hi), grown geometrically from 0
+    lo, hi = np.minimum(0.0, smu * h / r0), np.maximum(0.0, smu * h / r0)
+    for _ in range(200):
+        Flo, _ = _universal_f(lo, r0, vr0, alpha, smu, h)
+        Fhi, _ = _universal_f(hi, r0, vr0, alpha, smu, h)
+        grow_lo, grow_hi = Flo > 0, Fhi < 0
+        if not (grow_lo.any() or grow_hi.any()):
+            break
+        lo = np.where(grow_lo, 2 * lo - 1.0, lo)
+        hi = np.where(grow_hi, 2 * hi + 1.0, hi)
+    # first guesses: exact for a circle; for a hyperbola the anomaly grows like
+    # the logarithm of the time (r ~ v_inf t far out)
+    vinf2 = np.maximum(-alpha * mu, 1e-300)
+    with np.errstate(invalid="ignore"):
+        hyp = np.sign(h) * smu * np.log1p(np.sqrt(vinf2) * np.abs(h) / r0) / np.sqrt(vinf2)
+    chi = np.where(alpha > 0, smu * alpha * h, np.where(alpha < 0, hyp, smu * h / r0))
+    chi = np.clip(chi, lo, hi)
+    dx_old = hi - lo
     for _ in range(max_iter):
-        z = alpha * chi * chi
-        C, S = stumpff_c(z), stumpff_s(z)
-        F = r0 * vr0 / smu * chi * chi * C + (1 - alpha * r0) * chi ** 3 * S + r0 * chi - smu * h
-        dF = r0 * vr0 / smu * chi * (1 - z * S) + (1 - alpha * r0) * chi * chi * C + r0
-        step = F / dF
-        chi = chi - step
-        if np.all(np.abs(step) <= 1e-15 * np.maximum(np.abs(chi), 1e-300)):
+        F, dF = _universal_f(chi, r0, vr0, alpha, smu, h)
+        lo = np.where(F <= 0, chi, lo)
+        hi = np.where(F >= 0, chi, hi)
+        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+            newton = chi - F / dF
+            # bisect when Newton leaves the bracket or shrinks it too slowly
+            slow = np.abs(2 * F) > np.abs(dx_old * dF)
+        inside = np.isfinite(newton) & (newton > lo) & (newton < hi) & ~slow
+        new = np.where(inside, newton, 0.5 * (lo + hi))
+        dx_old = np.abs(new - chi)
+        done = (np.abs(new - chi) <= 1e-15 * np.abs(new)) | (F == 0)
+        chi = new
+        if done.all():
             break
     z = alpha * chi * chi
     C, S = stumpff_c(z), stumpff_s(z)

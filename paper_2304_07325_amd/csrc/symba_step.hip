@@ -110,7 +110,13 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
     const double beta = 2.0 / r0 - (vx * vx + vy * vy + vz * vz);
     const double eta = x * vx + y * vy + z * vz;
     const double zeta = 1.0 - beta * r0;
+    // first guess: h / r0 for short arcs and ellipses; on a hyperbola the
+    // variable grows like log(v_inf t) / v_inf (r ~ v_inf t far out)
     double s = h / r0, c0, c1, c2, c3;
+    if (beta < 0.0) {
+        const double vinf = sqrt(-beta);
+        s = copysign(log1p(vinf * fabs(h) / r0) / vinf, h);
+    }
     for (int it = 0; it < 40; ++it) {
         stumpff(beta * s * s, c0, c1, c2, c3);
         const double F = s * (r0 * c1 + s * (eta * c2 + s * c3)) - h;

@@ -127,3 +127,34 @@ def test_energy_of_the_accuracy_disk(ora, screen):
         worst = max(worst, abs(S.energy(r.state(), d.n_massive) - e0) / abs(e0))
     assert worst < 1e-8, worst
     r.close()
+
+
+def test_kepler_drift_of_every_conic(ora):
+    """Massless bodies (no kick, no Sun drift) on ellipses up to e = 0.95,
+    near-parabolic and hyperbolic orbits, over arcs from a small fraction of
+    an orbit to several orbits: the device's Kepler drift (Danby's universal
+    variable, Laguerre-Conway) against the oracle's (Curtis' universal
+    anomaly, Newton)."""
+    rng = np.random.default_rng(11)
+    n = 640
+    x = rng.normal(size=(n, 3))
+    x *= (rng.uniform(0.5, 30.0, n) / np.linalg.norm(x, axis=1))[:, None]
+    r = np.linalg.norm(x, axis=1)
+    v = rng.normal(size=(n, 3))
+    # speeds from deep ellipses through the parabola (sqrt(2/r)) to hyperbolae
+    v *= (np.sqrt(2.0 / r) * rng.uniform(0.2, 2.5, n) / np.linalg.norm(v, axis=1))[:, None]
+    v[:40] *= (np.sqrt(2.0 / r[:40]) / np.linalg.norm(v[:40], axis=1))[:, None] * (1 + rng.uniform(-1e-9, 1e-9, 40))[:, None]
+    s = dict(x=x[:, 0].copy(), y=x[:, 1].copy(), z=x[:, 2].copy(), vx=v[:, 0].copy(), vy=v[:, 1].copy(),
+             vz=v[:, 2].copy(), m=np.zeros(n), rh=np.zeros(n))
+    for h in (0.05, 7.0, 300.0, -40.0):
+        G.say("kepler drift conics h", h)
+        rr = Runner(s, 0, h)
+        rr.step()
+        got = rr.state()
+        rr.close()
+        xw, vw = S.kepler_drift(x, v, h)
+        gx = np.stack([got["x"], got["y"], got["z"]], 1)
+        gv = np.stack([got["vx"], got["vy"], got["vz"]], 1)
+        ex = np.linalg.norm(gx - xw, axis=1) / np.linalg.norm(xw, axis=1)
+        ev = np.linalg.norm(gv - vw, axis=1) / np.linalg.norm(vw, axis=1)
+        assert ex.max() < 1e-11 and ev.max() < 1e-11, (h, ex.max(), ev.max())

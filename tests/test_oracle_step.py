@@ -111,3 +111,23 @@ def test_massless_step_is_the_kepler_drift():
     assert not acc.any()
     np.testing.assert_array_equal(np.stack([s1["x"], s1["y"], s1["z"]], 1), x)
     np.testing.assert_array_equal(np.stack([s1["vx"], s1["vy"], s1["vz"]], 1), v)
+
+
+def test_kepler_drift_every_conic_keeps_invariants():
+    """Ellipses, near-parabolae and hyperbolae over short and very long arcs:
+    the drift keeps each orbit's energy and angular momentum."""
+    rng = np.random.default_rng(11)
+    n = 400
+    x = rng.normal(size=(n, 3))
+    x *= (rng.uniform(0.5, 30.0, n) / np.linalg.norm(x, axis=1))[:, None]
+    r = np.linalg.norm(x, axis=1)
+    v = rng.normal(size=(n, 3))
+    v *= (np.sqrt(2.0 / r) * rng.uniform(0.2, 2.5, n) / np.linalg.norm(v, axis=1))[:, None]
+    v[:30] *= (np.sqrt(2.0 / r[:30]) / np.linalg.norm(v[:30], axis=1))[:, None]
+    en = lambda x, v: 0.5 * np.sum(v * v, 1) - 1 / np.linalg.norm(x, axis=1)
+    scale = 1 / np.linalg.norm(x, axis=1)
+    for h in (0.05, 7.0, 300.0, -40.0):
+        xn, vn = S.kepler_drift(x, v, h)
+        assert np.isfinite(xn).all() and np.isfinite(vn).all()
+        assert (np.abs(en(xn, vn) - en(x, v)) / scale).max() < 1e-11
+        np.testing.assert_allclose(np.cross(xn, vn), np.cross(x, v), rtol=0, atol=1e-10)
