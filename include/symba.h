@@ -116,6 +116,14 @@ typedef struct {
     const double *rh;
 } symba_mstate;
 
+/* One simulation of a step batch (symba_step_batch). */
+typedef struct {
+    symba_mstate state;
+    int64_t n, n_m;
+    double h, rcrit_factor;
+    symba_out out;
+} symba_step_problem;
+
 /* One independent problem of a batch. */
 typedef struct {
     symba_state state;
@@ -189,6 +197,12 @@ const char *symba_strerror(int code);
  * reversible).  Errors and asynchrony as symba_kick_encounter. */
 int symba_step(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, double h,
                double rcrit_factor, const symba_out *out, void *stream);
+
+/* symba_step for many independent simulations in one set of launches, each
+ * with its own h; every simulation's state and outputs are the same bits as
+ * its own symba_step call would give.  Graph-capturable after a first call
+ * of the same shape (the descriptors are staged in pinned memory). */
+int symba_step_batch(symba_ctx *ctx, const symba_step_problem *steps, int32_t n_problems, void *stream);
 
 /* Host-only helper (no device work): the task list of the folded trapezoid
  * for n, n_m and a tile size of 64*rows bodies, in the order a single call

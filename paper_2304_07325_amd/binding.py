@@ -39,6 +39,11 @@ class symba_mstate(ctypes.Structure):
     _fields_ = [(k, _P) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rh")]
 
 
+class symba_step_problem(ctypes.Structure):
+    _fields_ = [("state", symba_mstate), ("n", _I64), ("n_m", _I64), ("h", _D), ("rcrit_factor", _D),
+                ("out", symba_out)]
+
+
 class symba_problem(ctypes.Structure):
     _fields_ = [("state", symba_state), ("n", _I64), ("n_m", _I64), ("dt", _D),
                 ("rcrit_factor", _D), ("out", symba_out)]
@@ -46,7 +51,7 @@ class symba_problem(ctypes.Structure):
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
-           "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step")
+           "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step", "symba_step_batch")
 
 
 class SymbaError(RuntimeError):
@@ -69,6 +74,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                          ctypes.POINTER(symba_out), _P]
     lib.symba_step.restype = ctypes.c_int
     lib.symba_step.argtypes = [_P, ctypes.POINTER(symba_mstate), _I64, _I64, _D, _D, ctypes.POINTER(symba_out), _P]
+    lib.symba_step_batch.restype = ctypes.c_int
+    lib.symba_step_batch.argtypes = [_P, ctypes.POINTER(symba_step_problem), ctypes.c_int32, _P]
     lib.symba_kick_encounter_batch.restype = ctypes.c_int
     lib.symba_kick_encounter_batch.argtypes = [_P, ctypes.POINTER(symba_problem), ctypes.c_int32, _P]
     lib.symba_strerror.restype = ctypes.c_char_p
@@ -229,6 +236,20 @@ class Context:
                               ctypes.byref(o), _stream_handle(stream))
         _check(rc, "symba_step")
         return out
+
+    def step_batch(self, problems, stream=None):
+        """symba_step_batch: problems = list of (device state, n_m, h, rcrit_factor, Outputs)."""
+        arr = (symba_step_problem * len(problems))()
+        for k, (state, n_m, h, f, out) in enumerate(problems):
+            _state_struct(state)
+            arr[k].state = symba_mstate(*(state[key].data_ptr() for key in STATE_KEYS))
+            arr[k].n = int(state["x"].numel())
+            arr[k].n_m = int(n_m)
+            arr[k].h = float(h)
+            arr[k].rcrit_factor = float(f)
+            arr[k].out = out.c_struct()
+        _check(lib().symba_step_batch(self._h, arr, len(problems), _stream_handle(stream)), "symba_step_batch")
+        return [p[4] for p in problems]
 
     def autotune(self, state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs | None = None,
                  stream=None) -> int:

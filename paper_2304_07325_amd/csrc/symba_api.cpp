@@ -21,7 +21,12 @@ struct symba_ctx {
     int32_t *parent = nullptr;   // [max_n] union-find offsets, zero between calls
     int32_t *touched = nullptr;  // [max_n]
     int32_t *blk_groups = nullptr;  // [max_n / kFinBodies + max_problems] groups per final-kernel body block
-    double *mom = nullptr;          // [2][step_blocks(max_n)][3] momentum partial sums of symba_step
+    double *mom = nullptr;          // [2][mom_blocks][3] momentum partial sums of symba_step(_batch)
+    int64_t mom_blocks = 0;         // step_blocks(max_n) + max_problems
+    symba::StepDesc *steps_dev = nullptr;     // [max_problems] drift descriptors of a step batch
+    symba::StepDesc *steps_pinned = nullptr;
+    hipEvent_t steps_done = nullptr;
+    bool steps_pending = false;
     int2 *pairs = nullptr;       // [max_pairs]
     int4 *sorted = nullptr;      // [max_pairs]
     int32_t *bcnt = nullptr;     // [max_n]
@@ -265,11 +270,16 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
     c->max_pairs = max_pairs;
     c->max_problems = kMaxProblems;
     c->max_boxes = max_n / symba::kWave + 2 * (int64_t)kMaxProblems;
+    c->mom_blocks = symba::step_blocks(max_n) + kMaxProblems;
     bool ok = hipMalloc(&c->parent, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->touched, sizeof(int32_t) * max_n) == hipSuccess &&
               hipMalloc(&c->blk_groups, sizeof(int32_t) * (max_n / symba::kFinBodies + kMaxProblems)) ==
                   hipSuccess &&
-              hipMalloc(&c->mom, sizeof(double) * 6 * symba::step_blocks(max_n)) == hipSuccess &&
+              hipMalloc(&c->mom, sizeof(double) * 6 * (symba::step_blocks(max_n) + kMaxProblems)) == hipSuccess &&
+              hipMalloc(&c->steps_dev, sizeof(symba::StepDesc) * kMaxProblems) == hipSuccess &&
+              hipHostMalloc(&c->steps_pinned, sizeof(symba::StepDesc) * kMaxProblems, hipHostMallocDefault) ==
+                  hipSuccess &&
+              hipEventCreateWithFlags(&c->steps_done, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&c->pairs, sizeof(int2) * max_pairs) == hipSuccess &&
               hipMalloc(&c->sorted, sizeof(int4) * max_pairs) == hipSuccess &&
               hipMalloc(&c->bcnt, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -313,6 +323,9 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->touched);
     (void)hipFree(c->blk_groups);
     (void)hipFree(c->mom);
+    (void)hipFree(c->steps_dev);
+    if (c->steps_pinned) (void)hipHostFree(c->steps_pinned);
+    if (c->steps_done) (void)hipEventDestroy(c->steps_done);
     (void)hipFree(c->pairs);
     (void)hipFree(c->sorted);
     (void)hipFree(c->bcnt);
@@ -403,7 +416,8 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
     }
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
     const symba::TileGroup g{rows, field_rows, binned, screen32(c), 0, 1, 0, d.n_tasks};
-    if (drifts && symba::launch_drifts(*drifts, (hipStream_t)stream) != hipSuccess) return SYMBA_EDEVICE;
+    if (drifts && symba::launch_drifts(*drifts, nullptr, 0, drifts->nblk, (hipStream_t)stream) != hipSuccess)
+        return SYMBA_EDEVICE;
     hipError_t e = symba::launch_step(&d, nullptr, 1, &g, 1, binned, symba::final_blocks(n, kScatterBlocks), cfg,
                                       (hipStream_t)stream, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
@@ -437,15 +451,21 @@ int symba_step(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, doub
     sd.sun_h = 0.5 * h;
     sd.kepler_h = h;
     sd.mom0 = c->mom;
-    sd.mom1 = c->mom + 3 * symba::step_blocks(c->max_n);
+    sd.mom1 = c->mom + 3 * c->mom_blocks;
+    sd.blk_base = 0;
+    sd.nblk = symba::step_blocks(n);
     const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
     double *const kick[3] = {s->vx, s->vy, s->vz};
     return evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, kick, 0.5 * h, &sd);
 }
 
-int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t n_problems,
-                               void *stream) {
-    if (!c || !probs || n_problems < 1 || n_problems > c->max_problems) return SYMBA_EINVAL;
+namespace {
+
+// The batch evaluation; with `steps` (the same problems as steps, in the same
+// order) the drifts run first and each problem's final kernel applies the
+// closing half kick.
+int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, void *stream,
+               const symba_step_problem *steps) {
     int64_t total_n = 0;
     for (int32_t k = 0; k < n_problems; ++k) {
         const symba_problem &q = probs[k];
@@ -496,6 +516,12 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
             groups.push_back(symba::TileGroup{rows[k], frows[k], bins[k], screen32(c), s, s, task_total, 0});
         Desc &d = ds[s];
         fill_desc(d, q.state, q.out, q.n, q.n_m, q.dt, q.rcrit_factor, plans[s], frows[k]);
+        if (steps) {
+            d.kvx = steps[k].state.vx;
+            d.kvy = steps[k].state.vy;
+            d.kvz = steps[k].state.vz;
+            d.kick_h = 0.5 * steps[k].h;
+        }
         d.task_base = task_total;
         d.partial = c->partial + partial_off;
         d.parent = c->parent + body_off;
@@ -523,6 +549,35 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
         groups.back().n_tasks += d.n_tasks;
     }
     hipStream_t st = (hipStream_t)stream;
+    if (steps) {  // the drift descriptors, in the caller's order, each problem a range of blocks
+        if (c->steps_pending && hipEventSynchronize(c->steps_done) != hipSuccess) return SYMBA_EDEVICE;
+        int64_t blk = 0;
+        for (int32_t k = 0; k < n_problems; ++k) {
+            const symba_step_problem &q = steps[k];
+            symba::StepDesc &sd = c->steps_pinned[k];
+            sd = symba::StepDesc{};
+            sd.x = q.state.x; sd.y = q.state.y; sd.z = q.state.z;
+            sd.vx = q.state.vx; sd.vy = q.state.vy; sd.vz = q.state.vz; sd.m = q.state.m;
+            sd.ax = q.out.ax; sd.ay = q.out.ay; sd.az = q.out.az;
+            sd.n = q.n;
+            sd.n_tri = q.n_m >= q.n - 1 ? q.n : q.n_m;
+            sd.kick_h = 0.5 * q.h;
+            sd.sun_h = 0.5 * q.h;
+            sd.kepler_h = q.h;
+            sd.mom0 = c->mom;
+            sd.mom1 = c->mom + 3 * c->mom_blocks;
+            sd.blk_base = blk;
+            sd.nblk = symba::step_blocks(q.n);
+            blk += sd.nblk;
+        }
+        if (hipMemcpyAsync(c->steps_dev, c->steps_pinned, sizeof(symba::StepDesc) * n_problems,
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipEventRecord(c->steps_done, st) != hipSuccess)
+            return SYMBA_EDEVICE;
+        c->steps_pending = true;
+        if (symba::launch_drifts(c->steps_pinned[0], c->steps_dev, n_problems, blk, st) != hipSuccess)
+            return SYMBA_EDEVICE;
+    }
     const bool same = c->descs_last.size() == ds.size() &&
                       std::memcmp(c->descs_last.data(), ds.data(), sizeof(Desc) * ds.size()) == 0;
     if (!same) {
@@ -538,6 +593,32 @@ int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t
     hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, groups.data(), (int)groups.size(),
                                       n_binned, fin_total, cfg, st, timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
+}
+
+}  // namespace
+
+int symba_kick_encounter_batch(symba_ctx *c, const symba_problem *probs, int32_t n_problems,
+                               void *stream) {
+    if (!c || !probs || n_problems < 1 || n_problems > c->max_problems) return SYMBA_EINVAL;
+    return batch_impl(c, probs, n_problems, stream, nullptr);
+}
+
+int symba_step_batch(symba_ctx *c, const symba_step_problem *steps, int32_t n_problems, void *stream) {
+    if (!c || !steps || n_problems < 1 || n_problems > c->max_problems) return SYMBA_EINVAL;
+    std::vector<symba_problem> probs((size_t)n_problems);
+    for (int32_t k = 0; k < n_problems; ++k) {
+        const symba_step_problem &q = steps[k];
+        const symba_mstate &m = q.state;
+        if (!m.x || !m.y || !m.z || !m.vx || !m.vy || !m.vz || !m.m || !m.rh || !std::isfinite(q.h))
+            return SYMBA_EINVAL;
+        probs[k].state = symba_state{m.x, m.y, m.z, m.vx, m.vy, m.vz, m.m, m.rh};
+        probs[k].n = q.n;
+        probs[k].n_m = q.n_m;
+        probs[k].dt = std::fabs(q.h);
+        probs[k].rcrit_factor = q.rcrit_factor;
+        probs[k].out = q.out;
+    }
+    return batch_impl(c, probs.data(), n_problems, stream, steps);
 }
 
 int symba_read_timing(symba_ctx *c, double *tiles_ms, double *finalize_ms, int64_t *calls) {

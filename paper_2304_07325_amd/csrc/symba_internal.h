@@ -100,13 +100,16 @@ struct StepDesc {
     const double *ax, *ay, *az;         // accelerations of the first kick
     int64_t n, n_tri;                   // bodies; massive bodies [0, n_tri)
     double kick_h, sun_h, kepler_h;     // h/2, h/2, h
-    double *mom0, *mom1;                // [step_blocks(n)][3] momentum partial sums
+    double *mom0, *mom1;                // [launch blocks][3] momentum partial sums (indexed by launch block)
+    int64_t blk_base, nblk;             // this problem's blocks [blk_base, blk_base + nblk) of the launch
 };
 
 // Blocks of the drift kernels for n bodies, and their launch (first kick,
-// Sun drift, Kepler drift, Sun drift).
+// Sun drift, Kepler drift, Sun drift): one problem (`one`, list null) or the
+// n_list problems of a device array whose blocks tile [0, total_blocks).
 int64_t step_blocks(int64_t n);
-hipError_t launch_drifts(const StepDesc &s, hipStream_t stream);
+hipError_t launch_drifts(const StepDesc &one, const StepDesc *list, int n_list, int64_t total_blocks,
+                         hipStream_t stream);
 
 // Problems [p0, p1) of a launch that share a tile size and binning: their tasks are
 // [task_begin, task_begin + n_tasks) of the launch's task numbering.

@@ -8,8 +8,9 @@
 //   Sun drift   x_i += (h/2) P, P = sum over massive bodies of m_i v_i;
 //   Kepler      each body on its two-body orbit about the Sun for h.
 // Three launches do the first kick and the drifts (k_kick_momentum,
-// k_sun_kepler, k_sun); the evaluation at the new positions follows, and the
-// final kick is an epilogue of its final kernel.  P is summed in a fixed
+// k_sun_kepler, k_sun), for one problem or a batch (each problem owning a
+// range of the launch's blocks); the evaluation at the new positions
+// follows, and the final kick is an epilogue of its final kernel.  P is summed in a fixed
 // order (per-block partial sums, then every block adds the partials in the
 // same order), so every block sees the same bits and the step is
 // reproducible.
@@ -52,11 +53,12 @@ __device__ __forceinline__ void write_momentum(const StepDesc &s, double *part, 
     }
 }
 
-// P from the blocks' partial sums, in the same order in every block.
-__device__ __forceinline__ void read_momentum(const double *part, int nblk, double &px, double &py, double &pz) {
+// P from the problem's blocks' partial sums, in the same order in every block.
+__device__ __forceinline__ void read_momentum(const StepDesc &s, const double *part, double &px, double &py,
+                                              double &pz) {
     __shared__ double red[kStepWaves];
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += kStepThreads) {
+    for (int64_t k = s.blk_base + threadIdx.x; k < s.blk_base + s.nblk; k += kStepThreads) {
         a += part[3 * k];
         b += part[3 * k + 1];
         c += part[3 * k + 2];
@@ -140,9 +142,32 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
     z = nz;
 }
 
+// The problem of launch block b: `one`, or the last of the list whose first
+// block is not above b.
+template <bool LIST>
+__device__ __forceinline__ const StepDesc &problem(const StepDesc &one, const StepDesc *list, int n_list) {
+    if (!LIST) return one;
+    int lo = 0, hi = n_list - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (list[mid].blk_base <= (int64_t)blockIdx.x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return list[lo];
+}
+
+__device__ __forceinline__ int64_t body_of(const StepDesc &s) {
+    return ((int64_t)blockIdx.x - s.blk_base) * kStepThreads + threadIdx.x;
+}
+
 // v += kick_h a, then this block's momentum partial sum.
-__global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc s) {
-    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc one, const StepDesc *list,
+                                                                int n_list) {
+    const StepDesc &s = problem<LIST>(one, list, n_list);
+    const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (k < s.n) {
         vx = s.vx[k] + s.kick_h * s.ax[k];
@@ -156,10 +181,13 @@ __global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc s
 }
 
 // x += sun_h P, Kepler drift for kepler_h, then the new momentum partial sum.
-__global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc s) {
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc one, const StepDesc *list,
+                                                             int n_list) {
+    const StepDesc &s = problem<LIST>(one, list, n_list);
     double px, py, pz;
-    read_momentum(s.mom0, (int)gridDim.x, px, py, pz);
-    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+    read_momentum(s, s.mom0, px, py, pz);
+    const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (k < s.n) {
         double x = s.x[k] + s.sun_h * px, y = s.y[k] + s.sun_h * py, z = s.z[k] + s.sun_h * pz;
@@ -178,10 +206,12 @@ __global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc s) {
 }
 
 // x += sun_h P with the momentum after the Kepler drift.
-__global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc s) {
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const StepDesc *list, int n_list) {
+    const StepDesc &s = problem<LIST>(one, list, n_list);
     double px, py, pz;
-    read_momentum(s.mom1, (int)gridDim.x, px, py, pz);
-    const int64_t k = (int64_t)blockIdx.x * kStepThreads + threadIdx.x;
+    read_momentum(s, s.mom1, px, py, pz);
+    const int64_t k = body_of(s);
     if (k < s.n) {
         s.x[k] += s.sun_h * px;
         s.y[k] += s.sun_h * py;
@@ -193,11 +223,18 @@ __global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc s) {
 
 int64_t step_blocks(int64_t n) { return (n + kStepThreads - 1) / kStepThreads; }
 
-hipError_t launch_drifts(const StepDesc &s, hipStream_t stream) {
-    const unsigned blocks = (unsigned)step_blocks(s.n);
-    hipLaunchKernelGGL(k_kick_momentum, dim3(blocks), dim3(kStepThreads), 0, stream, s);
-    hipLaunchKernelGGL(k_sun_kepler, dim3(blocks), dim3(kStepThreads), 0, stream, s);
-    hipLaunchKernelGGL(k_sun, dim3(blocks), dim3(kStepThreads), 0, stream, s);
+hipError_t launch_drifts(const StepDesc &one, const StepDesc *list, int n_list, int64_t total_blocks,
+                         hipStream_t stream) {
+    const unsigned blocks = (unsigned)(list ? total_blocks : one.nblk);
+    if (list) {
+        hipLaunchKernelGGL(k_kick_momentum<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
+        hipLaunchKernelGGL(k_sun_kepler<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
+        hipLaunchKernelGGL(k_sun<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
+    } else {
+        hipLaunchKernelGGL(k_kick_momentum<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, 0);
+        hipLaunchKernelGGL(k_sun_kepler<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, 0);
+        hipLaunchKernelGGL(k_sun<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, 0);
+    }
     return hipGetLastError();
 }
 

@@ -46,6 +46,7 @@ def test_errors_before_any_device_work():
     mst = B.symba_mstate()
     assert lib.symba_step(None, ctypes.byref(mst), 10, 9, 1.0, 3.0, ctypes.byref(out), None) == B.SYMBA_EINVAL
     assert lib.symba_step(None, None, 10, 9, float("nan"), 3.0, None, None) == B.SYMBA_EINVAL
+    assert lib.symba_step_batch(None, None, 1, None) == B.SYMBA_EINVAL
     assert lib.symba_strerror(B.SYMBA_ETOOBIG).decode().startswith("problem larger")
     assert lib.symba_plan_tasks(0, 0, 1, 1, None, 0) == -1
     assert lib.symba_plan_tasks(10, 11, 1, 1, None, 0) == -1

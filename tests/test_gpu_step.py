@@ -158,3 +158,41 @@ def test_kepler_drift_of_every_conic(ora):
         ex = np.linalg.norm(gx - xw, axis=1) / np.linalg.norm(xw, axis=1)
         ev = np.linalg.norm(gv - vw, axis=1) / np.linalg.norm(vw, axis=1)
         assert ex.max() < 1e-11 and ev.max() < 1e-11, (h, ex.max(), ev.max())
+
+
+def test_step_batch_matches_single_steps(ora):
+    """Simulations of uneven size, all-massive and field-heavy, stepped
+    together by symba_step_batch (with their own steps h) for several
+    rounds: every state, acceleration and pair list is the same bits as
+    stepping each alone with symba_step."""
+    from paper_2304_07325_amd import binding as B
+    import torch
+    specs = [(700, 699, 0.5), (300, 30, 0.2), (1500, 1499, 0.1), (65, 64, 1.0), (2000, 200, 0.3)]
+    sims = [dg.make_disk(n, nm, "hot", 40 + k).state(0) for k, (n, nm, _) in enumerate(specs)]
+    G.say("step batch", len(specs))
+    alone = []
+    for (n, nm, yr), s in zip(specs, sims):
+        r = Runner(s, nm, yr * dg.YEAR)
+        r.step(3)
+        alone.append((r.state(), r.out.to_host()))
+        r.close()
+    total = sum(n for n, _, _ in specs)
+    ctx = B.Context(max_n=total, max_pairs=1 << 17)
+    sts = [B.to_device_state(s) for s in sims]
+    outs = [B.Outputs(n, 1 << 13) for n, _, _ in specs]   # the pair scratch of the context is shared out
+    for (n, nm, yr), st, o in zip(specs, sts, outs):
+        ctx.kick_encounter(st, nm, yr * dg.YEAR, F, out=o)
+    probs = [(st, nm, yr * dg.YEAR, F, o) for (n, nm, yr), st, o in zip(specs, sts, outs)]
+    for _ in range(3):
+        ctx.step_batch(probs)
+    torch.cuda.synchronize()
+    for (want_s, want_o), st, o in zip(alone, sts, outs):
+        got = {k: v.cpu().numpy() for k, v in st.items()}
+        for k in KEYS:
+            assert got[k].tobytes() == want_s[k].tobytes(), k
+        g = o.to_host()
+        assert g["status"] == want_o["status"] == 0
+        assert g["acc"].tobytes() == want_o["acc"].tobytes()
+        assert np.array_equal(g["pair_i"], want_o["pair_i"]) and np.array_equal(g["pair_j"], want_o["pair_j"])
+        assert np.array_equal(g["group_id"], want_o["group_id"])
+    ctx.close()
