@@ -1,18 +1,22 @@
 """Continuous batching of kick/encounter steps over simulations kept in HBM.
 
-A request names one simulation and asks for one evaluation of the step on
-its current state.  The server keeps the simulations' states and output
-buffers resident in device memory within a byte budget.  When a batch needs
-room, it evicts the least recently used simulations that are not in that
-batch.  Whenever requests are waiting, the server runs every waiting request
-whose simulation is not already in the batch as one batched library call
-(symba_kick_encounter_batch).  A request arriving while a call runs joins the
-next call.  Each step of the path runs in the library's kernels; this module
-only chooses what goes into each call.
+A request names one simulation and asks either for one evaluation of the
+step on its current state (mode "evaluate", symba_kick_encounter_batch) or
+for one integrator step that advances it (mode "step", symba_step_batch).
+The server keeps the simulations' states and output buffers resident in
+device memory within a byte budget.  When a batch needs room, it evicts the
+least recently used simulations that are not in that batch (in step mode
+copying back the advanced state and its accelerations, which the next step
+starts from).  Whenever requests are waiting, the server runs every waiting
+request whose simulation is not already in the batch as one batched library
+call.  A request arriving while a call runs joins the next call.  Each step
+of the path runs in the library's kernels; this module only chooses what
+goes into each call.
 
 Results do not depend on batching: the library gives every problem the
-tile size of a single call, so a simulation's outputs are bit-identical
-whether it runs alone or with any other simulations.
+tile size of a single call, so a simulation's outputs (and in step mode its
+trajectory) are bit-identical whether it runs alone or with any other
+simulations.
 """
 from __future__ import annotations
 
@@ -37,12 +41,13 @@ def pair_capacity(n: int) -> int:
 
 @dataclass
 class _Sim:
-    state: dict            # host SoA arrays
+    state: dict            # host SoA arrays (in step mode: as of the last eviction)
     n: int
     n_m: int
     scratch: int           # library scratch in a batch (symba_scratch_bytes)
     dev: dict | None = None
     out: B.Outputs | None = None
+    acc: np.ndarray | None = None   # step mode: accelerations at `state`, kept while evicted
 
     @property
     def resident_bytes(self) -> int:
@@ -61,7 +66,10 @@ class Server:
     """
 
     def __init__(self, sims, budget_bytes: int, dt: float, rcrit_factor: float,
-                 max_batch_bodies: int | None = None, device: str = "cuda"):
+                 max_batch_bodies: int | None = None, device: str = "cuda", mode: str = "evaluate"):
+        if mode not in ("evaluate", "step"):
+            raise ValueError("mode is 'evaluate' or 'step'")
+        self.mode = mode
         self.device = device
         self.dt = float(dt)
         self.f = float(rcrit_factor)
@@ -95,6 +103,9 @@ class Server:
     # -- residency -----------------------------------------------------------
     def _evict(self, k: int):
         s = self.sims[k]
+        if self.mode == "step":  # the simulation has moved: keep its state and accelerations
+            s.state = {key: v.cpu().numpy() for key, v in s.dev.items()}
+            s.acc = s.out.acc.cpu().numpy()
         s.dev = None
         s.out = None
         self.resident -= s.resident_bytes
@@ -114,6 +125,11 @@ class Server:
         s = self.sims[k]
         s.dev = B.to_device_state(s.state, self.device)
         s.out = B.Outputs(s.n, pair_capacity(s.n), device=self.device)
+        if self.mode == "step":  # a step starts from the accelerations at the current positions
+            if s.acc is None:
+                self.ctx.kick_encounter(s.dev, s.n_m, abs(self.dt), self.f, out=s.out)
+            else:
+                s.out.acc.copy_(torch.from_numpy(s.acc))
         self.resident += s.resident_bytes
         self.lru[k] = None
         self.uploads += 1
@@ -148,7 +164,10 @@ class Server:
             else:
                 self.lru.move_to_end(k)
         probs = [(self.sims[k].dev, self.sims[k].n_m, self.dt, self.f, self.sims[k].out) for k in sim_ids]
-        self.ctx.kick_encounter_batch(probs, stream=stream)
+        if self.mode == "step":
+            self.ctx.step_batch(probs, stream=stream)
+        else:
+            self.ctx.kick_encounter_batch(probs, stream=stream)
 
     def outputs(self, k: int) -> B.Outputs:
         return self.sims[k].out

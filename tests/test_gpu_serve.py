@@ -65,3 +65,55 @@ def test_served_outputs_match_single_calls(budget):
         assert stats["evictions"] > 0
     print(budget, stats)
     server.close()
+
+
+def test_served_steps_match_stepping_alone():
+    """Step mode under a budget that forces evictions: after the c-th request
+    for a simulation, its state and accelerations are the same bits as after c
+    steps of that simulation alone (evicted simulations are copied back and
+    resume where they stopped)."""
+    import torch
+    from paper_2304_07325_amd import binding as B
+    from paper_2304_07325_amd.serve import Server, pair_capacity
+    specs = [(700, 699, 0.5), (300, 30, 0.2), (1500, 1499, 0.1), (65, 64, 1.0), (2000, 200, 0.3), (1100, 1099, 0.4)]
+    sims = [(dg.make_disk(n, nm, "hot", 60 + k).state(0), nm) for k, (n, nm, _) in enumerate(specs)]
+    h = 0.25 * dg.YEAR
+    rng = np.random.default_rng(9)
+    ids = rng.integers(0, len(sims), 40)
+    t = np.sort(rng.uniform(0.0, 0.03, len(ids)))
+    counts = np.bincount(ids, minlength=len(sims))
+    G.say("serve step mode, requests", len(ids))
+    # every simulation stepped alone, the states after 1..counts[k] steps kept
+    want = []
+    ctx = B.Context(max_n=max(n for n, _, _ in specs), max_pairs=1 << 16)
+    for (s, nm), c in zip(sims, counts):
+        st = B.to_device_state(s)
+        out = B.Outputs(s["x"].size, pair_capacity(s["x"].size))
+        ctx.kick_encounter(st, nm, h, F, out=out)
+        seq = []
+        for _ in range(c):
+            ctx.step(st, nm, h, F, out)
+            torch.cuda.synchronize()
+            seq.append(({k: v.cpu().numpy() for k, v in st.items()}, out.to_host()))
+        want.append(seq)
+    ctx.close()
+    probe = Server(sims, 1 << 34, h, F, mode="step")
+    limit = probe.fixed_bytes + max(probe._need(k) for k in range(len(sims))) + 100_000
+    probe.close()
+    server = Server(sims, limit, h, F, mode="step")
+    done = np.zeros(len(sims), dtype=int)
+
+    def check(r, k, out):
+        st, ref = want[k][done[k]]
+        got = {key: v.cpu().numpy() for key, v in server.sims[k].dev.items()}
+        for key in ("x", "y", "z", "vx", "vy", "vz"):
+            assert got[key].tobytes() == st[key].tobytes(), f"request {r} (sim {k}, step {done[k] + 1}): {key}"
+        g = out.to_host()
+        assert g["acc"].tobytes() == ref["acc"].tobytes(), f"request {r}: acc differs"
+        assert np.array_equal(g["pair_i"], ref["pair_i"]) and np.array_equal(g["group_id"], ref["group_id"])
+        done[k] += 1
+
+    stats = server.serve(t, ids, on_complete=check)
+    assert (done == counts).all() and stats["evictions"] > 0
+    print(stats)
+    server.close()

@@ -1,4 +1,5 @@
 """Batch selection of the serving loop (host logic only, no GPU)."""
+import pytest
 from collections import deque
 
 from paper_2304_07325_amd.serve import pair_capacity, pick_batch
@@ -30,3 +31,9 @@ def test_later_small_request_fills_room_left():
     batch, rest = pick_batch(deque([(0, 0), (1, 1), (2, 2)]), [10, 10**6, 10], [5, 10**9, 5], budget=100,
                              max_bodies=10**9, max_pairs=10**9)
     assert batch == [(0, 0), (2, 2)] and list(rest) == [(1, 1)]
+
+
+def test_server_rejects_unknown_mode():
+    from paper_2304_07325_amd.serve import Server
+    with pytest.raises(ValueError):
+        Server([], 1 << 30, 1.0, 3.5, mode="drift")
