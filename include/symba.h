@@ -67,6 +67,20 @@ extern "C" {
                                    pair list, groups and accelerations are the same bits either way */
 #define SYMBA_OPT_TIMING 5      /* 1 = record HIP events around the kernels of every call (symba_read_timing) */
 #define SYMBA_OPT_BIN 6         /* spatial binning: 0 = by problem size, 1 = never, 2 = always */
+#define SYMBA_OPT_ACC 7         /* what symba_kick_encounter(_batch) writes to ax, ay, az: SYMBA_ACC_* below.
+                                   symba_step and symba_step_batch ignore it: their kicks and the
+                                   accelerations they leave are the interaction term */
+
+/* Values of SYMBA_OPT_ACC.  The paper's loop (Sec. 2) sums the pair
+ * interactions, the kick term of the democratic heliocentric splitting
+ * (Duncan, Levison & Lee 1998, cited in Sec. 1); the Sun's terms belong to
+ * the drifts of that splitting and are added here only on request. */
+#define SYMBA_ACC_INTERACTION 0  /* the pair interaction sum only (default): what the kick of the
+                                    democratic heliocentric map applies */
+#define SYMBA_ACC_HELIO 1        /* the full heliocentric acceleration (Sun's mass 1, G = 1):
+                                    a_i - x_i / |x_i|^3 - sum_j m_j x_j / |x_j|^3, the sum over
+                                    the massive bodies (the Sun's pull and the indirect term of
+                                    the accelerated heliocentric frame) */
 
 /* Values of SYMBA_OPT_SCREEN. */
 #define SYMBA_SCREEN_AUTO 0  /* the library's choice: the FP32 screen */
@@ -141,10 +155,11 @@ int symba_ctx_create(symba_ctx **ctx, int device, int64_t max_n, int64_t max_pai
 /* Free the context and its scratch (after all work on it has completed). */
 int symba_ctx_destroy(symba_ctx *ctx);
 
-/* Set a tuning option (SYMBA_OPT_*).  Returns SYMBA_EINVAL for an unknown
- * option or value.  Options change speed only: pairs, groups and status are
- * unaffected; the tile sizes change the order in which the accelerations are
- * summed, so their bits (not their tolerance) depend on them. */
+/* Set an option (SYMBA_OPT_*).  Returns SYMBA_EINVAL for an unknown option
+ * or value.  SYMBA_OPT_ACC chooses what the accelerations hold; the other
+ * options change speed only: pairs, groups and status are unaffected, and the
+ * tile sizes change the order in which the accelerations are summed, so
+ * their bits (not their tolerance) depend on them. */
 int symba_set_option(symba_ctx *ctx, int option, int value);
 
 /* One kick/encounter evaluation (Sec. 2 of the paper): accelerations over the

@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_PKG, "libsymba.so")
 
 SYMBA_OK, SYMBA_EINVAL, SYMBA_ENOMEM, SYMBA_EDEVICE, SYMBA_ETOOBIG = 0, 1, 2, 3, 4
 STATUS_CAPACITY, STATUS_NONFINITE = 1, 2
-OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN = 1, 2, 4, 5, 6
+OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN, OPT_ACC = 1, 2, 4, 5, 6, 7
 SCREEN_AUTO, SCREEN_FP32, SCREEN_FP64 = 0, 1, 2
+ACC_INTERACTION, ACC_HELIO = 0, 1
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

@@ -47,7 +47,8 @@ struct symba_ctx {
     hipEvent_t upload_done = nullptr;
     bool upload_pending = false;
     // options
-    int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0;
+    int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0, opt_acc = 0;
+    double *ind = nullptr;  // [max_n / kIndBodies + max_problems][3] indirect-term partial sums (SYMBA_ACC_HELIO)
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
     // timing events (SYMBA_OPT_TIMING): three per timed call
@@ -277,6 +278,7 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
                   hipSuccess &&
               hipMalloc(&c->mom, sizeof(double) * 6 * (symba::step_blocks(max_n) + kMaxProblems)) == hipSuccess &&
               hipMalloc(&c->steps_dev, sizeof(symba::StepDesc) * kMaxProblems) == hipSuccess &&
+              hipMalloc(&c->ind, sizeof(double) * 3 * (max_n / symba::kIndBodies + kMaxProblems)) == hipSuccess &&
               hipHostMalloc(&c->steps_pinned, sizeof(symba::StepDesc) * kMaxProblems, hipHostMallocDefault) ==
                   hipSuccess &&
               hipEventCreateWithFlags(&c->steps_done, hipEventDisableTiming) == hipSuccess &&
@@ -324,6 +326,7 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->blk_groups);
     (void)hipFree(c->mom);
     (void)hipFree(c->steps_dev);
+    (void)hipFree(c->ind);
     if (c->steps_pinned) (void)hipHostFree(c->steps_pinned);
     if (c->steps_done) (void)hipEventDestroy(c->steps_done);
     (void)hipFree(c->pairs);
@@ -364,9 +367,12 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             c->opt_bin = value;
             return SYMBA_OK;
         case SYMBA_OPT_TIMING:
-            if (value != SYMBA_SCREEN_AUTO && value != SYMBA_SCREEN_FP32 && value != SYMBA_SCREEN_FP64)
-                return SYMBA_EINVAL;
+            if (value != 0 && value != 1) return SYMBA_EINVAL;
             c->opt_timing = value;
+            return SYMBA_OK;
+        case SYMBA_OPT_ACC:
+            if (value != SYMBA_ACC_INTERACTION && value != SYMBA_ACC_HELIO) return SYMBA_EINVAL;
+            c->opt_acc = value;
             return SYMBA_OK;
         case SYMBA_OPT_SCREEN:
             if (value != SYMBA_SCREEN_AUTO && value != SYMBA_SCREEN_FP32 && value != SYMBA_SCREEN_FP64)
@@ -406,13 +412,17 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
     d.nb = symba::bucket_count(n);
     d.ctr = c->ctr;
     d.stats = c->stats;
-    const symba::LaunchCfg cfg{kScatterBlocks, kCloseBlocks};
+    symba::LaunchCfg cfg{kScatterBlocks, kCloseBlocks, 0};
     d.fin_base = 0;
     if (kick) {
         d.kvx = kick[0];
         d.kvy = kick[1];
         d.kvz = kick[2];
         d.kick_h = kick_h;
+    } else if (c->opt_acc == SYMBA_ACC_HELIO) {
+        d.ind = c->ind;
+        d.n_ind = ceil_div(d.n_tri, symba::kIndBodies);
+        cfg.ind_blocks = d.n_ind;
     }
     const int binned = wire_binning(c, d, use_bin(c, n, n_m), 0, 0);
     const symba::TileGroup g{rows, field_rows, binned, screen32(c), 0, 1, 0, d.n_tasks};
@@ -504,10 +514,10 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
     }
     int rc = grow_partial(c, partial_total);
     if (rc != SYMBA_OK) return rc;
-    int64_t task_total = 0, fin_total = 0, body_off = 0, blk_off = 0, pair_off = 0, box_off = 0;
+    int64_t task_total = 0, fin_total = 0, body_off = 0, blk_off = 0, pair_off = 0, box_off = 0, ind_off = 0;
     int n_binned = 0;
     size_t partial_off = 0;
-    const symba::LaunchCfg cfg{kScatterBlocksBatch, kCloseBlocksBatch};
+    symba::LaunchCfg cfg{kScatterBlocksBatch, kCloseBlocksBatch, 0};
     for (int32_t s = 0; s < n_problems; ++s) {
         const int k = order[s];
         const symba_problem &q = probs[k];
@@ -521,6 +531,11 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
             d.kvy = steps[k].state.vy;
             d.kvz = steps[k].state.vz;
             d.kick_h = 0.5 * steps[k].h;
+        } else if (c->opt_acc == SYMBA_ACC_HELIO) {
+            d.ind = c->ind + 3 * ind_off;
+            d.n_ind = ceil_div(d.n_tri, symba::kIndBodies);
+            d.ind_base = ind_off;
+            ind_off += d.n_ind;
         }
         d.task_base = task_total;
         d.partial = c->partial + partial_off;
@@ -548,6 +563,7 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
         groups.back().p1 = s + 1;
         groups.back().n_tasks += d.n_tasks;
     }
+    cfg.ind_blocks = ind_off;
     hipStream_t st = (hipStream_t)stream;
     if (steps) {  // the drift descriptors, in the caller's order, each problem a range of blocks
         if (c->steps_pending && hipEventSynchronize(c->steps_done) != hipSuccess) return SYMBA_EDEVICE;

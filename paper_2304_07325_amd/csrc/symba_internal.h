@@ -91,6 +91,12 @@ struct Desc {
     // final (null outside symba_step)
     double *kvx, *kvy, *kvz;
     double kick_h;
+    // full heliocentric output (SYMBA_ACC_HELIO): per-block partial sums of
+    // m x / |x|^3 over the massive bodies, written by k_indirect before the
+    // final kernel; null for the interaction term alone
+    double *ind;          // [n_ind][3]
+    int64_t n_ind;        // k_indirect blocks of this problem (kIndBodies massive bodies each)
+    int64_t ind_base;     // first global k_indirect block of this problem
 };
 
 // The drifts of a step (symba_step) before the evaluation at the new positions.
@@ -125,7 +131,10 @@ struct TileGroup {
 struct LaunchCfg {
     int scatter_blocks_per_problem;  // pair-scatter blocks per problem (final kernel)
     int close_blocks_per_problem;    // closing-kernel blocks per problem
+    int64_t ind_blocks;              // k_indirect blocks of all problems (0: interaction term only)
 };
+
+constexpr int kIndBodies = 256;  // massive bodies per k_indirect block (one per thread)
 
 // Folded triangle: block pair (I, J) with J = I + k (mod B) for offsets
 // k = 0 .. K - 1, K = (B - 1) / 2 + 1, plus, when B is even, the pairs

@@ -821,13 +821,15 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
     drain_rest(d, Q);  // after the barriers, as in the triangle tasks
 }
 
-// Problem owning global index `key` of the task list (which 0) or of the
-// final-kernel blocks (which 1): the last problem whose base is not above it.
+// Problem owning global index `key` of the task list (which 0), of the
+// final-kernel blocks (which 1) or of the k_indirect blocks (which 2): the
+// last problem whose base is not above it.
 __device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, int which) {
     int lo = 0, hi = n_desc - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t base = which == 0 ? descs[mid].task_base : descs[mid].fin_base;
+        const int64_t base =
+            which == 0 ? descs[mid].task_base : (which == 1 ? descs[mid].fin_base : descs[mid].ind_base);
         if (base <= key)
             lo = mid;
         else
@@ -1207,8 +1209,69 @@ struct FinLds {
 // threads (fixed ranges, combined in a fixed order: deterministic; field
 // bodies were summed completely by their field task and are only checked),
 // and each body's group label.
+// Sum over the block of one triple per thread, in a fixed order (shuffle
+// tree in each wave, then the waves in order); every thread gets the totals.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double red[3][kFinalizeThreads / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    __syncthreads();
+    if (lane() == 0) {
+        red[0][wave_id()] = a;
+        red[1][wave_id()] = b;
+        red[2][wave_id()] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int w = 0; w < kFinalizeThreads / kWave; ++w) {
+        a += red[0][w];
+        b += red[1][w];
+        c += red[2][w];
+    }
+}
+
+// Block b of a problem's k_indirect: the partial sum of m_j x_j / |x_j|^3
+// over its kIndBodies massive bodies, the indirect term of the accelerated
+// heliocentric frame (Sun's mass 1, G = 1).
+static_assert(kIndBodies == kFinalizeThreads, "k_indirect takes one body per thread");
+
+__device__ __forceinline__ void indirect_block(const Desc &d, int64_t b) {
+    if (b >= d.n_ind) return;
+    const int64_t j = b * kIndBodies + threadIdx.x;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
+    if (j < d.n_tri) {
+        const double px = d.x[j], py = d.y[j], pz = d.z[j];
+        const double r2 = px * px + py * py + pz * pz;
+        const double w = d.m[j] / (r2 * sqrt(r2));
+        cx = w * px;
+        cy = w * py;
+        cz = w * pz;
+    }
+    block_sum3(cx, cy, cz);
+    if (threadIdx.x == 0) {
+        d.ind[3 * b] = cx;
+        d.ind[3 * b + 1] = cy;
+        d.ind[3 * b + 2] = cz;
+    }
+}
+
 __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t lb) {
     const int tid = threadIdx.x;
+    // full heliocentric output: the indirect term, the problem's k_indirect
+    // partials added in the same order in every block
+    double a0x = 0.0, a0y = 0.0, a0z = 0.0;
+    if (d.ind) {
+        for (int64_t b = tid; b < d.n_ind; b += kFinalizeThreads) {
+            a0x += d.ind[3 * b];
+            a0y += d.ind[3 * b + 1];
+            a0z += d.ind[3 * b + 2];
+        }
+        block_sum3(a0x, a0y, a0z);
+    }
     auto &part = F.part;
     const int col = tid % kFinBodies, split = tid / kFinBodies;
     const int64_t pos = lb * kFinBodies + col;  // position in the binned order
@@ -1247,13 +1310,23 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
                 sy += part[s2][1][col];
                 sz += part[s2][2][col];
             }
-            d.ax[k] = sx;
-            d.ay[k] = sy;
-            d.az[k] = sz;
-        } else {
+        } else {  // a field body's sums, written by its field task
             sx = d.ax[k];
             sy = d.ay[k];
             sz = d.az[k];
+        }
+        if (d.ind) {  // the Sun's pull and the indirect term
+            const double px = d.x[k], py = d.y[k], pz = d.z[k];
+            const double r2 = px * px + py * py + pz * pz;
+            const double q = 1.0 / (r2 * sqrt(r2));
+            sx = sx - q * px - a0x;
+            sy = sy - q * py - a0y;
+            sz = sz - q * pz - a0z;
+        }
+        if (own_sum || d.ind) {
+            d.ax[k] = sx;
+            d.ay[k] = sy;
+            d.az[k] = sz;
         }
         if (d.kvx) {  // the step's closing half kick
             d.kvx[k] += d.kick_h * sx;
@@ -1407,6 +1480,13 @@ __global__ __launch_bounds__(kFinalizeThreads) void k_final_batch(const Desc *__
     final_block(F, d, blockIdx.x - d.fin_base, scatter_blocks);
 }
 
+__global__ __launch_bounds__(kFinalizeThreads) void k_indirect(const Desc d) { indirect_block(d, blockIdx.x); }
+
+__global__ __launch_bounds__(kFinalizeThreads) void k_indirect_batch(const Desc *__restrict__ descs, int n_desc) {
+    const Desc &d = descs[problem_of(descs, n_desc, blockIdx.x, 2)];
+    indirect_block(d, (int64_t)blockIdx.x - d.ind_base);
+}
+
 __global__ __launch_bounds__(kFinalizeThreads) void k_close(const Desc d, int blocks) {
     close_block(d, blockIdx.x, blocks);
 }
@@ -1467,6 +1547,14 @@ hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc
     }
     if (ev && hipEventRecord(ev[1], stream) != hipSuccess) return hipErrorUnknown;
     const int sb = cfg.scatter_blocks_per_problem, cb = cfg.close_blocks_per_problem;
+    if (cfg.ind_blocks > 0) {  // the indirect term's partial sums (full heliocentric output)
+        if (dd)
+            hipLaunchKernelGGL(k_indirect_batch, dim3((unsigned)cfg.ind_blocks), dim3(kFinalizeThreads), 0, stream,
+                               dd, n_desc);
+        else
+            hipLaunchKernelGGL(k_indirect, dim3((unsigned)cfg.ind_blocks), dim3(kFinalizeThreads), 0, stream, inl);
+        if (hipGetLastError() != hipSuccess) return hipErrorUnknown;
+    }
     if (dd)
         hipLaunchKernelGGL(k_final_batch, dim3((unsigned)n_fin_total), dim3(kFinalizeThreads), 0, stream, dd,
                            n_desc, sb);
