@@ -310,6 +310,31 @@ def bench_step(args, B, dg, torch):
         L = (m[:, None] * np.cross(x, v)).sum(0)
         return e, L
 
+    # eager steps on a copy, for the launch cost the graphs below remove
+    eager_n = min(2000, total)
+    st_e = B.to_device_state(s0)
+    ctx_e = B.Context(max_n=128, max_pairs=1 << 14)
+    out_e = B.Outputs(100, 1 << 13)
+    ctx_e.kick_encounter(st_e, nm, h, f, out=out_e)
+    for _ in range(20):
+        ctx_e.step(st_e, nm, h, f, out_e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(eager_n):
+        ctx_e.step(st_e, nm, h, f, out_e)
+    torch.cuda.synchronize()
+    eager_rate = eager_n / (time.perf_counter() - t0)
+    ctx_e.close()
+    # the run itself: graphs of graph_steps steps (the same bits as eager
+    # steps), the remainder of each chunk eager
+    graph_steps = 100
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(graph_steps):
+            ctx.step(st, nm, h, f, out, stream=side)
+    torch.cuda.synchronize()
     e0, L0 = invariants(s0)
     chunks, worst_e, worst_l = 50, 0.0, 0.0
     per = max(total // chunks, 1)
@@ -317,7 +342,9 @@ def bench_step(args, B, dg, torch):
     done = 0
     while done < total:
         k = min(per, total - done)
-        for _ in range(k):
+        for _ in range(k // graph_steps):
+            graph.replay()
+        for _ in range(k % graph_steps):
             ctx.step(st, nm, h, f, out)
         done += k
         torch.cuda.synchronize()
@@ -331,8 +358,10 @@ def bench_step(args, B, dg, torch):
                             "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
                             "angmom_rel_err_max": worst_l, "checkpoints": chunks,
                             "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
-                            "steps_per_s": done / wall}
-    log(f"accuracy disk: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s, energy err max "
+                            "steps_per_s": done / wall, "graph_steps": graph_steps,
+                            "eager_steps_per_s": eager_rate}
+    log(f"accuracy disk: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s ({done / wall:.0f} steps/s "
+        f"in graphs of {graph_steps}, {eager_rate:.0f} eager), energy err max "
         f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}")
     ctx.close()
     return res

@@ -9,8 +9,9 @@
 //   Kepler      each body on its two-body orbit about the Sun for h.
 // Three launches do the first kick and the drifts (k_kick_momentum,
 // k_sun_kepler, k_sun), for one problem or a batch (each problem owning a
-// range of the launch's blocks); the evaluation at the new positions
-// follows, and the final kick is an epilogue of its final kernel.  P is summed in a fixed
+// range of the launch's blocks), or one launch (k_drifts_block) for a single
+// problem of one block.  The evaluation at the new positions follows, and
+// the final kick is an epilogue of its final kernel.  P is summed in a fixed
 // order (per-block partial sums, then every block adds the partials in the
 // same order), so every block sees the same bits and the step is
 // reproducible.
@@ -163,10 +164,7 @@ __device__ __forceinline__ int64_t body_of(const StepDesc &s) {
 }
 
 // v += kick_h a, then this block's momentum partial sum.
-template <bool LIST>
-__global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc one, const StepDesc *list,
-                                                                int n_list) {
-    const StepDesc &s = problem<LIST>(one, list, n_list);
+__device__ __forceinline__ void kick_momentum(const StepDesc &s) {
     const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (k < s.n) {
@@ -181,10 +179,7 @@ __global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc o
 }
 
 // x += sun_h P, Kepler drift for kepler_h, then the new momentum partial sum.
-template <bool LIST>
-__global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc one, const StepDesc *list,
-                                                             int n_list) {
-    const StepDesc &s = problem<LIST>(one, list, n_list);
+__device__ __forceinline__ void sun_kepler(const StepDesc &s) {
     double px, py, pz;
     read_momentum(s, s.mom0, px, py, pz);
     const int64_t k = body_of(s);
@@ -206,9 +201,7 @@ __global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc one,
 }
 
 // x += sun_h P with the momentum after the Kepler drift.
-template <bool LIST>
-__global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const StepDesc *list, int n_list) {
-    const StepDesc &s = problem<LIST>(one, list, n_list);
+__device__ __forceinline__ void sun(const StepDesc &s) {
     double px, py, pz;
     read_momentum(s, s.mom1, px, py, pz);
     const int64_t k = body_of(s);
@@ -217,6 +210,35 @@ __global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const 
         s.y[k] += s.sun_h * py;
         s.z[k] += s.sun_h * pz;
     }
+}
+
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc one, const StepDesc *list,
+                                                                int n_list) {
+    kick_momentum(problem<LIST>(one, list, n_list));
+}
+
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc one, const StepDesc *list,
+                                                             int n_list) {
+    sun_kepler(problem<LIST>(one, list, n_list));
+}
+
+template <bool LIST>
+__global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const StepDesc *list, int n_list) {
+    sun(problem<LIST>(one, list, n_list));
+}
+
+// All three for a problem of one block (n <= kStepThreads): the same code in
+// one launch, the block's barriers standing in for the launch boundaries (a
+// thread reads back only its own body, and the momentum partial it reads was
+// written by this block), so the bits are those of the three launches.
+__global__ __launch_bounds__(kStepThreads) void k_drifts_block(const StepDesc one) {
+    kick_momentum(one);
+    __syncthreads();
+    sun_kepler(one);
+    __syncthreads();
+    sun(one);
 }
 
 }  // namespace
@@ -230,6 +252,8 @@ hipError_t launch_drifts(const StepDesc &one, const StepDesc *list, int n_list, 
         hipLaunchKernelGGL(k_kick_momentum<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
         hipLaunchKernelGGL(k_sun_kepler<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
         hipLaunchKernelGGL(k_sun<true>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, n_list);
+    } else if (blocks == 1) {  // launch latency dominates a problem this small
+        hipLaunchKernelGGL(k_drifts_block, dim3(1), dim3(kStepThreads), 0, stream, one);
     } else {
         hipLaunchKernelGGL(k_kick_momentum<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, 0);
         hipLaunchKernelGGL(k_sun_kepler<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, list, 0);

@@ -196,3 +196,34 @@ def test_step_batch_matches_single_steps(ora):
         assert np.array_equal(g["pair_i"], want_o["pair_i"]) and np.array_equal(g["pair_j"], want_o["pair_j"])
         assert np.array_equal(g["group_id"], want_o["group_id"])
     ctx.close()
+
+
+def test_step_graph_replays_match_eager():
+    """Twenty steps of the accuracy disk captured in a HIP graph and replayed
+    three times, with eager steps and synchronisations between the replays:
+    every replay leaves the state and accelerations of twenty eager steps,
+    bit for bit (the step allocates nothing and records no memset)."""
+    import torch
+    d = dg.make_accuracy_disk(n=100)
+    s, nm, h = d.state(0), d.n_massive, d.dt
+    G.say("step graph replays")
+    eager = Runner(s, nm, h)
+    graphed = Runner(s, nm, h)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for _ in range(20):
+            graphed.ctx.step(graphed.st, nm, h, F, graphed.out, stream=side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        eager.step(20)
+        got, want = graphed.state(), eager.state()
+        for k in KEYS:
+            assert got[k].tobytes() == want[k].tobytes(), (rep, k)
+        assert graphed.out.to_host()["acc"].tobytes() == eager.out.to_host()["acc"].tobytes(), rep
+    eager.close()
+    graphed.close()
