@@ -424,7 +424,9 @@ def bench_serve(args, dg, torch):
     that names a uniformly random simulation, served by continuous batching:
     latency from arrival to completion (host monotonic clock).  Run with a
     200 GB device budget (nothing is evicted) and again with 0.5 GB, which
-    keeps only part of the population resident."""
+    keeps only part of the population resident.  Then at saturation (every
+    request waiting from the start): served steps/s against the same requests
+    as plain per-simulation calls."""
     from paper_2304_07325_amd.serve import Server
     dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
     pop = dg.serving_population()
@@ -444,6 +446,32 @@ def bench_serve(args, dg, torch):
         log(f"serve {name}: p50 {stats['latency_ms']['p50']:.3f} ms p99 {stats['latency_ms']['p99']:.3f} ms, "
             f"{stats['steps_per_s']:.0f} steps/s, mean batch {stats['mean_batch']:.1f}, "
             f"uploads {stats['uploads']}, evictions {stats['evictions']}")
+    # saturation: every request already waiting at t = 0, served by continuous
+    # batching, against the same requests in the same order as plain
+    # per-simulation calls on the same resident simulations
+    import numpy as np
+    n_sat = max(args.serve_requests // 10, 1)
+    _, ids = dg.poisson_arrivals(args.serve_rate, n_sat, len(sims))
+    srv = Server(sims, 200 << 30, dt, f)
+    srv.preload()
+    torch.cuda.synchronize()
+    stats = srv.serve(np.zeros(n_sat), ids)
+    for k in ids[:20]:   # warm the plain path
+        srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in ids:
+        srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    pairs = stats["pairs_per_s"] * n_sat / stats["steps_per_s"]
+    srv.close()
+    res["saturated"] = {"requests": n_sat, "served_steps_per_s": stats["steps_per_s"],
+                        "served_pairs_per_s": stats["pairs_per_s"], "mean_batch": stats["mean_batch"],
+                        "calls": stats["calls"], "plain_steps_per_s": n_sat / plain_s,
+                        "plain_pairs_per_s": pairs / plain_s}
+    log(f"serve saturated: {stats['steps_per_s']:.0f} steps/s served (mean batch {stats['mean_batch']:.1f}) "
+        f"vs {n_sat / plain_s:.0f} steps/s as plain calls")
     return res
 
 
