@@ -499,8 +499,10 @@ def bench_batch(args, B, dg, torch):
         n_tri = n if nm >= n - 1 else nm
         cls = n_tri.bit_length() - 1
         if cls not in tuned:
-            tuned[cls] = ctx.autotune(st, nm, dt, f, out=o)
-    log("autotuned bodies per lane by size class 2^k: " + ", ".join(f"{k}:{v}" for k, v in sorted(tuned.items())))
+            ctx.autotune(st, nm, dt, f, out=o)
+            tuned[cls] = ctx.plan_for(n, nm)   # (bodies per lane, split diagonals)
+    log("autotuned (bodies per lane, split diagonals) by size class 2^k: " +
+        ", ".join(f"{k}:{v}" for k, v in sorted(tuned.items())))
     rounds = args.batch_rounds
 
     def plain_round():
@@ -511,7 +513,7 @@ def bench_batch(args, B, dg, torch):
         ctx.kick_encounter_batch(probs)
 
     res = {"disks": len(specs), "bodies": total_n, "pairs_per_round": total_pairs,
-           "autotuned_rows": {f"2^{k}": v for k, v in sorted(tuned.items())}}
+           "autotuned_plan": {f"2^{k}": {"rows": v[0], "split": v[1]} for k, v in sorted(tuned.items())}}
     for name, fn in (("plain", plain_round), ("batched", batch_round)):
         for _ in range(3):
             fn()

@@ -70,6 +70,10 @@ extern "C" {
 #define SYMBA_OPT_ACC 7         /* what symba_kick_encounter(_batch) writes to ax, ay, az: SYMBA_ACC_* below.
                                    symba_step and symba_step_batch ignore it: their kicks and the
                                    accelerations they leave are the interaction term */
+#define SYMBA_OPT_SPLIT 8       /* split diagonals of the folded triangle (R = 2 or 4): their block pairs run
+                                   as single tile pairs at the end of the tile kernel.  -1 = automatic
+                                   (the autotuner's choice, else a rule by launch depth), 0..8 = that many
+                                   (clamped to what the fold has) */
 
 /* Values of SYMBA_OPT_ACC.  The paper's loop (Sec. 2) sums the pair
  * interactions, the kick term of the democratic heliocentric splitting
@@ -239,16 +243,19 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
  * Any output pointer may be NULL. */
 int symba_read_stats(symba_ctx *ctx, int64_t *candidates, int64_t *flagged, int64_t *problems);
 
-/* Tile-size autotuner: runs the problem (arguments as symba_kick_encounter)
- * with every tile size (64, 128 and 256 massive bodies per block row), times
- * the calls with HIP events, and keeps the fastest size in the context for
- * every later problem of the same size class (the same power of two of
- * n_tri = N if N_m >= N - 1, else N_m), in single and batched calls alike,
- * unless SYMBA_OPT_TILE_ROWS forces a size.  Results stay within the same
- * tolerance whichever size runs (pairs and groups are exact); accelerations
- * are bit-reproducible for a given size.  Writes the outputs of a final call
- * with the chosen size, *chosen_rows (may be NULL) = bodies per lane (1, 2 or
- * 4).  Synchronizes the stream; do not call it under graph capture. */
+/* Autotuner of the tile size and the fold schedule: runs the problem
+ * (arguments as symba_kick_encounter) with every tile size (64, 128 and 256
+ * massive bodies per block row) and, for 128 and 256, with 0 to 3 split
+ * diagonals of the folded triangle (SYMBA_OPT_SPLIT), times the calls with
+ * HIP events, and keeps the fastest pair in the context for every later
+ * problem of the same size class (the same power of two of n_tri = N if
+ * N_m >= N - 1, else N_m), in single and batched calls alike, unless
+ * SYMBA_OPT_TILE_ROWS or SYMBA_OPT_SPLIT forces a choice.  Results stay
+ * within the same tolerance whichever plan runs (pairs and groups are
+ * exact); accelerations are bit-reproducible for a given plan.  Writes the
+ * outputs of a final call with the chosen plan, *chosen_rows (may be NULL)
+ * = bodies per lane (1, 2 or 4); symba_plan_for reports the split.
+ * Synchronizes the stream; do not call it under graph capture. */
 int symba_autotune(symba_ctx *ctx, const symba_state *s, int64_t n, int64_t n_m, double dt,
                    double rcrit_factor, const symba_out *out, void *stream, int32_t *chosen_rows);
 
@@ -260,6 +267,14 @@ int symba_autotune(symba_ctx *ctx, const symba_state *s, int64_t n, int64_t n_m,
  * many problems resident budget device memory before it batches them.
  * Returns -1 on invalid arguments. */
 int64_t symba_scratch_bytes(const symba_ctx *ctx, int64_t n, int64_t n_m, int64_t pair_cap);
+
+/* The plan a call on a problem of n bodies, n_m massive, would use now (the
+ * options and the autotuner's table as they stand): *rows = bodies per lane
+ * of the triangle tiles (1, 2 or 4), *split = split diagonals of the folded
+ * triangle (Sec. 2: the triangle mapped onto a rectangle; the tile pairs of
+ * the split diagonals run last).  Host only, no device work; either pointer
+ * may be NULL.  Returns SYMBA_EINVAL for a null context or invalid sizes. */
+int symba_plan_for(const symba_ctx *ctx, int64_t n, int64_t n_m, int32_t *rows, int32_t *split);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libsymba.so")
 
 SYMBA_OK, SYMBA_EINVAL, SYMBA_ENOMEM, SYMBA_EDEVICE, SYMBA_ETOOBIG = 0, 1, 2, 3, 4
 STATUS_CAPACITY, STATUS_NONFINITE = 1, 2
-OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN, OPT_ACC = 1, 2, 4, 5, 6, 7
+OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN, OPT_ACC, OPT_SPLIT = 1, 2, 4, 5, 6, 7, 8
 SCREEN_AUTO, SCREEN_FP32, SCREEN_FP64 = 0, 1, 2
 ACC_INTERACTION, ACC_HELIO = 0, 1
 
@@ -52,7 +52,8 @@ class symba_problem(ctypes.Structure):
 
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
-           "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step", "symba_step_batch")
+           "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step", "symba_step_batch",
+           "symba_plan_for")
 
 
 class SymbaError(RuntimeError):
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(symba_out), _P, ctypes.POINTER(ctypes.c_int32)]
     lib.symba_scratch_bytes.restype = _I64
     lib.symba_scratch_bytes.argtypes = [_P, _I64, _I64, _I64]
+    lib.symba_plan_for.restype = ctypes.c_int
+    lib.symba_plan_for.argtypes = [_P, _I64, _I64, _P, _P]
     lib.symba_plan_tasks.restype = _I64
     lib.symba_plan_tasks.argtypes = [_I64, _I64, ctypes.c_int32, ctypes.c_int32, _P, _I64]
     return lib
@@ -211,6 +214,13 @@ class Context:
         if v < 0:
             raise SymbaError("symba_scratch_bytes: invalid arguments")
         return int(v)
+
+    def plan_for(self, n: int, n_m: int):
+        """symba_plan_for: (bodies per lane, split diagonals) a call on a problem
+        of this size would use now."""
+        r, d = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().symba_plan_for(self._h, int(n), int(n_m), ctypes.byref(r), ctypes.byref(d)), "symba_plan_for")
+        return int(r.value), int(d.value)
 
     def kick_encounter(self, state: dict, n_m: int, dt: float, rcrit_factor: float,
                        out: Outputs | None = None, stream=None) -> Outputs:

@@ -48,9 +48,12 @@ struct symba_ctx {
     bool upload_pending = false;
     // options
     int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0, opt_acc = 0;
+    int opt_split = -1;  // split diagonals of the folded triangle, -1 = automatic
     double *ind = nullptr;  // [max_n / kIndBodies + max_problems][3] indirect-term partial sums (SYMBA_ACC_HELIO)
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
+    // split diagonals + 1 chosen with those rows by symba_autotune, 0 = not tuned
+    int tuned_split[64] = {};
     // timing events (SYMBA_OPT_TIMING): three per timed call
     std::vector<hipEvent_t> events;
     size_t timed_calls = 0;
@@ -59,6 +62,7 @@ struct symba_ctx {
 namespace {
 
 constexpr int kMaxProblems = 4096;
+constexpr int kMaxSplit = 8;  // most split diagonals SYMBA_OPT_SPLIT accepts
 // Pair-scatter blocks (final kernel) and closing blocks per problem: a single
 // call spreads them wide, a batch of many problems less so.
 constexpr int kScatterBlocks = 16, kCloseBlocks = 32;
@@ -123,13 +127,27 @@ int64_t tail_split(int64_t B, int rows) {
     return symba::split_diagonals(B, rows, SYMBA_TAIL_SPLIT);
 }
 
+// Split diagonals wanted for a problem of n_tri massive bodies run with
+// `rows`: SYMBA_OPT_SPLIT when set, else what symba_autotune chose for the
+// size class together with these rows, else -1 (the rule of tail_split).
+int split_for(const symba_ctx *c, int64_t n_tri, int rows) {
+    if (c->opt_split >= 0) return c->opt_split;
+    if (n_tri > 0) {
+        const int k = size_class(n_tri);
+        if (c->tuned_split[k] && c->tuned_rows[k] == rows) return c->tuned_split[k] - 1;
+    }
+    return -1;
+}
+
 struct Plan {
     int64_t n_rows, n_tri, B, n_split, n_whole, n_slots, n_tri_tasks, n_field_tasks, n_blk;
     int rows;
     size_t partial_doubles;
 };
 
-Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
+// split: split diagonals wanted (clamped to what the fold allows), -1 for
+// the rule of tail_split.
+Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows, int split) {
     Plan p{};
     p.n_rows = std::min(n_m, n - 1);
     p.n_tri = n_m >= n - 1 ? n : n_m;
@@ -138,7 +156,7 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows) {
     p.rows = rows;
     if (p.n_rows > 0) {
         p.B = (p.n_tri + S - 1) / S;
-        p.n_split = tail_split(p.B, rows);
+        p.n_split = split < 0 ? tail_split(p.B, rows) : symba::split_diagonals(p.B, rows, split);
         p.n_whole = symba::whole_count(p.B, p.n_split);
         p.n_tri_tasks = p.n_whole + p.n_split * p.B * rows * rows;
         p.n_slots = symba::partial_slots(p.B, rows, p.n_split);
@@ -370,6 +388,10 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             if (value != 0 && value != 1) return SYMBA_EINVAL;
             c->opt_timing = value;
             return SYMBA_OK;
+        case SYMBA_OPT_SPLIT:
+            if (value < -1 || value > kMaxSplit) return SYMBA_EINVAL;
+            c->opt_split = value;
+            return SYMBA_OK;
         case SYMBA_OPT_ACC:
             if (value != SYMBA_ACC_INTERACTION && value != SYMBA_ACC_HELIO) return SYMBA_EINVAL;
             c->opt_acc = value;
@@ -394,7 +416,7 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
     const int n_tri_guess = (int)(n_m >= n - 1 ? n : n_m);
     const int rows = rows_for(c, n_tri_guess);
     const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
-    const Plan p = make_plan(n, n_m, rows, field_rows);
+    const Plan p = make_plan(n, n_m, rows, field_rows, split_for(c, n_tri_guess, rows));
     int rc = grow_partial(c, p.partial_doubles);
     if (rc != SYMBA_OK) return rc;
     Desc d;
@@ -509,7 +531,8 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
     size_t partial_total = 0;
     for (int32_t s = 0; s < n_problems; ++s) {
         const symba_problem &q = probs[order[s]];
-        plans[s] = make_plan(q.n, q.n_m, rows[order[s]], frows[order[s]]);
+        const int64_t n_tri = q.n_m >= q.n - 1 ? q.n : q.n_m;
+        plans[s] = make_plan(q.n, q.n_m, rows[order[s]], frows[order[s]], split_for(c, n_tri, rows[order[s]]));
         partial_total += plans[s].partial_doubles;
     }
     int rc = grow_partial(c, partial_total);
@@ -661,7 +684,7 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
     if (n < 1 || n_m < 0 || n_m > n || (rows != 1 && rows != 2 && rows != 4) ||
         (field_rows != 1 && field_rows != 2) || cap < 0 || (cap > 0 && !tasks))
         return -1;
-    const Plan p = make_plan(n, n_m, rows, field_rows);
+    const Plan p = make_plan(n, n_m, rows, field_rows, -1);
     const int64_t total = p.n_tri_tasks + p.n_field_tasks;
     for (int64_t f = 0; f < std::min(total, cap); ++f) {
         const int64_t t = symba::task_in_order(p.n_tri_tasks, total, f);
@@ -718,46 +741,68 @@ int symba_autotune(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, d
         if (e0) (void)hipEventDestroy(e0);
         return SYMBA_EDEVICE;
     }
-    const int saved_rows = c->opt_rows, saved_timing = c->opt_timing;
+    const int saved_rows = c->opt_rows, saved_timing = c->opt_timing, saved_split = c->opt_split;
     c->opt_timing = 0;
+    // tile sizes, and with 2 or 4 rows the fold's tail split: 0 to 3 split
+    // diagonals (distinct plans only: the fold clamps what it cannot split)
     constexpr int kRows[3] = {1, 2, 4};
     constexpr int kReps = 3;
-    int best = 0, rc = SYMBA_OK;
+    int best = 0, best_split = 0, rc = SYMBA_OK;
     float best_ms = 0.f;
     for (int r : kRows) {
-        c->opt_rows = r;
-        rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);  // warm-up (and buffer growth)
-        if (rc != SYMBA_OK) break;
-        float ms = 0.f;
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = SYMBA_EDEVICE; break; }
-        for (int k = 0; k < kReps && rc == SYMBA_OK; ++k)
-            rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
-        if (rc != SYMBA_OK) break;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = SYMBA_EDEVICE;
-            break;
+        const int64_t B = (n_tri + (int64_t)r * symba::kWave - 1) / ((int64_t)r * symba::kWave);
+        for (int D = 0; D <= 3 && rc == SYMBA_OK; ++D) {
+            if (D > 0 && symba::split_diagonals(B, r, D) < D) break;
+            c->opt_rows = r;
+            c->opt_split = D;
+            rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);  // warm-up, buffer growth
+            if (rc != SYMBA_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = SYMBA_EDEVICE; break; }
+            for (int k = 0; k < kReps && rc == SYMBA_OK; ++k)
+                rc = symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
+            if (rc != SYMBA_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = SYMBA_EDEVICE;
+                break;
+            }
+            if (best == 0 || ms < best_ms) {
+                best = r;
+                best_split = D;
+                best_ms = ms;
+            }
         }
-        if (best == 0 || ms < best_ms) {
-            best = r;
-            best_ms = ms;
-        }
+        if (rc != SYMBA_OK) break;
     }
     c->opt_rows = saved_rows;
     c->opt_timing = saved_timing;
+    c->opt_split = saved_split;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SYMBA_OK) return rc;
     c->tuned_rows[size_class(n_tri)] = best;
+    c->tuned_split[size_class(n_tri)] = best_split + 1;
     if (chosen_rows) *chosen_rows = best;
     // leave the problem's outputs as a call with the tuned size writes them
     return symba_kick_encounter(c, s, n, n_m, dt, rcrit_factor, out, stream);
 }
 
+int symba_plan_for(const symba_ctx *c, int64_t n, int64_t n_m, int32_t *rows, int32_t *split) {
+    if (!c || n < 1 || n_m < 0 || n_m > n) return SYMBA_EINVAL;
+    const int64_t n_tri = n_m >= n - 1 ? n : n_m;
+    const int r = rows_for(c, n_tri);
+    const Plan p = make_plan(n, n_m, r, field_rows_for(n - n_tri, c->opt_field_rows), split_for(c, n_tri, r));
+    if (rows) *rows = r;
+    if (split) *split = (int32_t)p.n_split;
+    return SYMBA_OK;
+}
+
 int64_t symba_scratch_bytes(const symba_ctx *c, int64_t n, int64_t n_m, int64_t pair_cap) {
     if (!c || n < 1 || n_m < 0 || n_m > n || pair_cap < 0) return -1;
     const int64_t n_tri = n_m >= n - 1 ? n : n_m;
-    const Plan p = make_plan(n, n_m, rows_for(c, n_tri), field_rows_for(n - n_tri, c->opt_field_rows));
+    const int rows = rows_for(c, n_tri);
+    const Plan p = make_plan(n, n_m, rows, field_rows_for(n - n_tri, c->opt_field_rows), split_for(c, n_tri, rows));
     const int64_t per_body = 5 * (int64_t)sizeof(int32_t) +                                 // parent, touched, buckets
                              (use_bin(c, n, n_m) ? 3 * (int64_t)sizeof(int32_t) + 8 * (int64_t)sizeof(double) +
                                                        symba::kBoxDoubles * (int64_t)sizeof(double) / symba::kWave

@@ -161,6 +161,6 @@ def test_binding_constants_match_header():
     import re
     text = open(os.path.join(ROOT, "include", "symba.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SYMBA_(\w+)\s+(-?\d+)", text)}
-    for name in ("OPT_TILE_ROWS", "OPT_FIELD_ROWS", "OPT_SCREEN", "OPT_TIMING", "OPT_BIN", "OPT_ACC",
+    for name in ("OPT_TILE_ROWS", "OPT_FIELD_ROWS", "OPT_SCREEN", "OPT_TIMING", "OPT_BIN", "OPT_ACC", "OPT_SPLIT",
                  "SCREEN_AUTO", "SCREEN_FP32", "SCREEN_FP64", "ACC_INTERACTION", "ACC_HELIO"):
         assert getattr(B, name) == defs[name], name

@@ -348,9 +348,9 @@ def test_hot50k_full_size(ctx, ora):
 
 
 def test_autotune_chooses_a_size_and_stays_exact(ora):
-    """The autotuner times every tile size, keeps one for the size class, and
-    the outputs of its final call and of a later call of the same size are
-    bit-identical and match the oracle."""
+    """The autotuner times every tile size and tail split, keeps one plan for
+    the size class, and the outputs of its final call and of a later call of
+    the same size are bit-identical and match the oracle."""
     from paper_2304_07325_amd import binding as B
     s = G.dense_state(3000, seed=61, box=6.0)
     G.say("autotune n=3000")
@@ -359,6 +359,9 @@ def test_autotune_chooses_a_size_and_stays_exact(ora):
     out = B.Outputs(3000, 1 << 15)
     rows = ctx.autotune(dev, 2999, DT, F, out=out)
     assert rows in (1, 2, 4)
+    plan_rows, split = ctx.plan_for(3000, 2999)
+    assert plan_rows == rows and 0 <= split <= 3 and (rows > 1 or split == 0)
+    assert ctx.plan_for(2500, 2499) == (rows, split)     # the same size class
     tuned = out.to_host()
     ref = ora.kick_encounter(s, 2999, DT, F)
     G.check_pairs_groups(tuned, ref)
@@ -367,8 +370,44 @@ def test_autotune_chooses_a_size_and_stays_exact(ora):
     assert again["acc"].tobytes() == tuned["acc"].tobytes()
     forced = B.Context(max_n=4096, max_pairs=1 << 16)
     forced.set_option(B.OPT_TILE_ROWS, rows)
+    forced.set_option(B.OPT_SPLIT, split)
     assert G.run_gpu(forced, s, 2999, DT, F, pair_cap=1 << 15)["acc"].tobytes() == tuned["acc"].tobytes()
     forced.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("rows", [2, 4])
+def test_every_tail_split_is_exact(ora, rows):
+    """The fold schedule with 0 to 3 split diagonals (SYMBA_OPT_SPLIT): the
+    plan reports what the fold allows, every schedule matches the oracle, and
+    a batch with the same forced schedule gives each problem its single
+    call's bits."""
+    import torch
+    from paper_2304_07325_amd import binding as B
+    s = G.dense_state(3000, seed=62, box=6.0)
+    s2 = G.dense_state(1400, seed=63, box=4.0)
+    ref = ora.kick_encounter(s, 2999, DT, F)
+    for D in range(4):
+        G.say("tail split", rows, D)
+        ctx = B.Context(max_n=4400, max_pairs=1 << 16)
+        ctx.set_option(B.OPT_TILE_ROWS, rows)
+        ctx.set_option(B.OPT_SPLIT, D)
+        assert ctx.plan_for(3000, 2999) == (rows, D)
+        got = G.run_gpu(ctx, s, 2999, DT, F, pair_cap=1 << 14)
+        G.check_pairs_groups(got, ref)
+        G.check_acc(s, 2999, got["acc"], ref["acc"])
+        alone2 = G.run_gpu(ctx, s2, 1399, DT, F, pair_cap=1 << 14)
+        sts = [B.to_device_state(s), B.to_device_state(s2)]
+        outs = [B.Outputs(3000, 1 << 14), B.Outputs(1400, 1 << 14)]
+        ctx.kick_encounter_batch([(sts[0], 2999, DT, F, outs[0]), (sts[1], 1399, DT, F, outs[1])])
+        torch.cuda.synchronize()
+        assert outs[0].to_host()["acc"].tobytes() == got["acc"].tobytes()
+        assert outs[1].to_host()["acc"].tobytes() == alone2["acc"].tobytes()
+        ctx.close()
+    ctx = B.Context(max_n=64)
+    for bad in (-2, 9):
+        with pytest.raises(Exception):
+            ctx.set_option(B.OPT_SPLIT, bad)
     ctx.close()
 
 
