@@ -171,6 +171,7 @@ def main():
     ctx = B.Context(max_n=max(n, 1), max_pairs=max(16 * n, 1 << 16))
     outs = [B.Outputs(n, max(16 * n, 1 << 16)) for _ in range(2)]
     stream = torch.cuda.current_stream()
+    plan = ctx.plan_for(n, n_m)   # tile rows and split diagonals the library picks for this size
 
     for s in range(args.warmup):
         ctx.kick_encounter(states[s % evals], n_m, dt, f, out=outs[s % 2])
@@ -236,7 +237,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: cold planetesimal disk (Sec. 3 recipe), N={n}, N_m={n_m}, "
                                f"dt=0.5 yr, rcrit=3 Hill radii, {evals} Kepler-advanced states resident in HBM",
-                   "pairs_per_step": pairs, "parallelism": "single GPU"},
+                   "pairs_per_step": pairs, "parallelism": "single GPU",
+                   "plan": dict(zip(("rows", "split"), plan))},
         "latency_ms": latency,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic_from_profiles(),
