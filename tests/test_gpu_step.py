@@ -160,24 +160,28 @@ def test_kepler_drift_of_every_conic(ora):
         assert ex.max() < 1e-11 and ev.max() < 1e-11, (h, ex.max(), ev.max())
 
 
-def test_step_batch_matches_single_steps(ora):
+@pytest.mark.parametrize("binned", [False, True])
+def test_step_batch_matches_single_steps(ora, binned):
     """Simulations of uneven size, all-massive and field-heavy, stepped
     together by symba_step_batch (with their own steps h) for several
     rounds: every state, acceleration and pair list is the same bits as
-    stepping each alone with symba_step."""
+    stepping each alone with symba_step (also with every problem binned,
+    where each closing kick maps binned positions back)."""
     from paper_2304_07325_amd import binding as B
     import torch
     specs = [(700, 699, 0.5), (300, 30, 0.2), (1500, 1499, 0.1), (65, 64, 1.0), (2000, 200, 0.3)]
     sims = [dg.make_disk(n, nm, "hot", 40 + k).state(0) for k, (n, nm, _) in enumerate(specs)]
-    G.say("step batch", len(specs))
+    G.say("step batch", len(specs), "binned" if binned else "")
     alone = []
     for (n, nm, yr), s in zip(specs, sims):
-        r = Runner(s, nm, yr * dg.YEAR)
+        r = Runner(s, nm, yr * dg.YEAR, binned=binned)
         r.step(3)
         alone.append((r.state(), r.out.to_host()))
         r.close()
     total = sum(n for n, _, _ in specs)
     ctx = B.Context(max_n=total, max_pairs=1 << 17)
+    if binned:
+        ctx.set_option(B.OPT_BIN, 2)
     sts = [B.to_device_state(s) for s in sims]
     outs = [B.Outputs(n, 1 << 13) for n, _, _ in specs]   # the pair scratch of the context is shared out
     for (n, nm, yr), st, o in zip(specs, sts, outs):
