@@ -41,6 +41,8 @@ def _declare(lib):
     lib.oracle_accel_body.argtypes = [_I64, _I64, _I64] + [_P] * 5
     lib.oracle_encounter.restype = ctypes.c_int
     lib.oracle_encounter.argtypes = [_D] * 16
+    lib.oracle_encounter_list.restype = ctypes.c_int
+    lib.oracle_encounter_list.argtypes = [_I64] + [_P] * 7 + [_D, _D, _I64, _P, _P, _P]
     lib.oracle_pairs.restype = _I64
     lib.oracle_pairs.argtypes = [_I64, _I64] + [_P] * 7 + [_D, _D, _P, _P, _I64]
     lib.oracle_partners.restype = _I64
@@ -108,6 +110,17 @@ class Oracle:
     def encounter(self, bi, bj, dt, f):
         """bi, bj: (x, y, z, vx, vy, vz, rh) of the two bodies."""
         return bool(self.L.oracle_encounter(*map(float, bi), *map(float, bj), float(dt), float(f)))
+
+    def encounter_list(self, s, pi, pj, dt, f):
+        """The predicate on each listed pair (pi[k], pj[k]) of state s: bool array."""
+        arrs = [_f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "rh")]
+        pi, pj = _i32(pi), _i32(pj)
+        flag = np.zeros(pi[0].size, np.uint8)
+        rc = self.L.oracle_encounter_list(arrs[0][0].size, *(a[1] for a in arrs), float(dt), float(f),
+                                          pi[0].size, pi[1], pj[1], flag.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle_encounter_list: invalid arguments")
+        return flag.astype(bool)
 
     def pairs(self, s, n_m, dt, f, cap=None):
         arrs = [_f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "rh")]

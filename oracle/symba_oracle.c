@@ -146,6 +146,23 @@ int64_t oracle_pairs(int64_t n, int64_t n_m,
     return count;
 }
 
+int oracle_encounter_list(int64_t n, const double *x, const double *y, const double *z,
+                          const double *vx, const double *vy, const double *vz, const double *rh,
+                          double dt, double rcrit_factor, int64_t n_pairs,
+                          const int32_t *pair_i, const int32_t *pair_j, uint8_t *flag)
+{
+    if (n < 1 || n_pairs < 0 || !(dt >= 0.0) || !(rcrit_factor > 0.0))
+        return -1;
+    for (int64_t k = 0; k < n_pairs; ++k) {
+        int64_t i = pair_i[k], j = pair_j[k];
+        if (i < 0 || i >= n || j < 0 || j >= n)
+            return -1;
+        flag[k] = (uint8_t)oracle_encounter(x[i], y[i], z[i], vx[i], vy[i], vz[i], rh[i],
+                                            x[j], y[j], z[j], vx[j], vy[j], vz[j], rh[j], dt, rcrit_factor);
+    }
+    return 0;
+}
+
 int64_t oracle_partners(int64_t i, int64_t n, int64_t n_m,
                         const double *x, const double *y, const double *z,
                         const double *vx, const double *vy, const double *vz, const double *rh,

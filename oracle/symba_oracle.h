@@ -45,6 +45,14 @@ int oracle_encounter(double xi, double yi, double zi, double vxi, double vyi, do
                      double xj, double yj, double zj, double vxj, double vyj, double vzj, double rhj,
                      double dt, double rcrit_factor);
 
+/* The encounter predicate on each listed pair (pair_i[k], pair_j[k]) of a
+ * state, body i taken first as in oracle_pairs: flag[k] = 1 if flagged, else
+ * 0.  Returns 0, or -1 for invalid arguments or an index outside [0, n). */
+int oracle_encounter_list(int64_t n, const double *x, const double *y, const double *z,
+                          const double *vx, const double *vy, const double *vz, const double *rh,
+                          double dt, double rcrit_factor, int64_t n_pairs,
+                          const int32_t *pair_i, const int32_t *pair_j, uint8_t *flag);
+
 /* Flagged pairs of the trapezoid in lexicographic (i, j) order, i < j.
  * Stores at most `cap` pairs; returns the true count (may exceed cap). */
 int64_t oracle_pairs(int64_t n, int64_t n_m,

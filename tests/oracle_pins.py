@@ -332,6 +332,11 @@ def check_pair_enumeration(o):
                     expect.append((i, j))
         got = list(zip(pi.tolist(), pj.tolist()))
         assert got == expect, f"pairs n={n} n_m={n_m}: {got[:10]} vs {expect[:10]}"
+        # the predicate over a list of pairs: the same decisions, pair by pair
+        ii = np.array([i for i in range(rows_count(n, n_m)) for j in range(i + 1, n)], np.int32)
+        jj = np.array([j for i in range(rows_count(n, n_m)) for j in range(i + 1, n)], np.int32)
+        flags = o.encounter_list(s, ii, jj, dt, f)
+        assert list(zip(ii[flags].tolist(), jj[flags].tolist())) == expect
         assert len(set(got)) == len(got)
         fused = o.kick_encounter(s, n_m, dt, f)
         assert np.array_equal(fused["pair_i"], pi) and np.array_equal(fused["pair_j"], pj)
