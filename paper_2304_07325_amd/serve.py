@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import time
 from collections import OrderedDict, deque
+from contextlib import nullcontext
 from dataclasses import dataclass
 
 import numpy as np
@@ -153,21 +154,24 @@ class Server:
 
     def run_batch(self, sim_ids, stream=None):
         """One batched call over distinct simulations, loading the ones that are
-        not resident (evicting the least recently used others to make room)."""
-        keep = set(sim_ids)
-        scratch = sum(self.sims[k].scratch for k in keep)
-        loads = sum(self.sims[k].resident_bytes for k in keep if k not in self.lru)
-        self._make_room(loads + scratch, keep)
-        for k in sim_ids:
-            if k not in self.lru:
-                self._load(k)
+        not resident (evicting the least recently used others to make room).
+        With `stream`, the evictions' copies, the uploads and the call are all
+        ordered on that stream."""
+        with torch.cuda.stream(stream) if stream is not None else nullcontext():
+            keep = set(sim_ids)
+            scratch = sum(self.sims[k].scratch for k in keep)
+            loads = sum(self.sims[k].resident_bytes for k in keep if k not in self.lru)
+            self._make_room(loads + scratch, keep)
+            for k in sim_ids:
+                if k not in self.lru:
+                    self._load(k)
+                else:
+                    self.lru.move_to_end(k)
+            probs = [(self.sims[k].dev, self.sims[k].n_m, self.dt, self.f, self.sims[k].out) for k in sim_ids]
+            if self.mode == "step":
+                self.ctx.step_batch(probs)
             else:
-                self.lru.move_to_end(k)
-        probs = [(self.sims[k].dev, self.sims[k].n_m, self.dt, self.f, self.sims[k].out) for k in sim_ids]
-        if self.mode == "step":
-            self.ctx.step_batch(probs, stream=stream)
-        else:
-            self.ctx.kick_encounter_batch(probs, stream=stream)
+                self.ctx.kick_encounter_batch(probs)
 
     def outputs(self, k: int) -> B.Outputs:
         return self.sims[k].out

@@ -117,3 +117,48 @@ def test_served_steps_match_stepping_alone():
     assert (done == counts).all() and stats["evictions"] > 0
     print(stats)
     server.close()
+
+
+def test_run_batch_on_a_side_stream():
+    """Step mode driven through run_batch on a stream of its own, under a
+    budget that evicts a simulation on every call and with no host
+    synchronisation between calls: the evictions' copies, the uploads and the
+    steps are ordered on that stream, so each simulation ends where stepping
+    it alone ends."""
+    import torch
+    from paper_2304_07325_amd import binding as B
+    from paper_2304_07325_amd.serve import Server, pair_capacity
+    specs = [(600, 599), (300, 30), (900, 899), (450, 449)]
+    sims = [(dg.make_disk(n, nm, "hot", 80 + k).state(0), nm) for k, (n, nm) in enumerate(specs)]
+    h = 0.3 * dg.YEAR
+    order = [0, 1, 2, 3, 0, 2, 1, 3, 3, 0, 2, 1, 0]
+    G.say("run_batch on a side stream", len(order))
+    want = []
+    ctx = B.Context(max_n=max(n for n, _ in specs), max_pairs=1 << 16)
+    for k, (s, nm) in enumerate(sims):
+        st = B.to_device_state(s)
+        out = B.Outputs(s["x"].size, pair_capacity(s["x"].size))
+        ctx.kick_encounter(st, nm, h, F, out=out)
+        for _ in range(order.count(k)):
+            ctx.step(st, nm, h, F, out)
+        torch.cuda.synchronize()
+        want.append({key: v.cpu().numpy() for key, v in st.items()})
+    ctx.close()
+    probe = Server(sims, 1 << 34, h, F, mode="step")
+    limit = probe.fixed_bytes + max(probe._need(k) for k in range(len(sims))) + 1000
+    probe.close()
+    server = Server(sims, limit, h, F, mode="step")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    for k in order:
+        server.run_batch([k], stream=side)
+    torch.cuda.synchronize()
+    assert server.evictions >= len(order) // 2   # most calls evict another simulation
+    for k in range(len(sims)):
+        if server.sims[k].dev is not None:
+            got = {key: v.cpu().numpy() for key, v in server.sims[k].dev.items()}
+        else:
+            got = server.sims[k].state
+        for key in ("x", "y", "z", "vx", "vy", "vz"):
+            assert got[key].tobytes() == want[k][key].tobytes(), (k, key)
+    server.close()
