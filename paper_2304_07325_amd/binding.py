@@ -153,7 +153,15 @@ class Outputs:
         return out
 
 
-def _state_struct(st: dict) -> symba_state:
+def _state_struct(st: dict, out: "Outputs | None" = None) -> symba_state:
+    """Checks a state (and the outputs it is written to) before its pointers
+    reach the library, which takes every array to hold n = len(x) bodies."""
+    n = st["x"].numel()
+    for k in STATE_KEYS:
+        if st[k].numel() != n:
+            raise ValueError(f"state[{k!r}] has {st[k].numel()} elements, state['x'] has {n}")
+    if out is not None and out.n < n:
+        raise ValueError(f"the outputs hold {out.n} bodies, the state has {n}")
     for k in STATE_KEYS:
         t = st[k]
         if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
@@ -228,7 +236,7 @@ class Context:
         n = int(state["x"].numel())
         if out is None:
             out = Outputs(n, min(self.max_pairs, max(4 * n, 4096)), device=state["x"].device)
-        st = _state_struct(state)
+        st = _state_struct(state, out)
         o = out.c_struct()
         rc = lib().symba_kick_encounter(self._h, ctypes.byref(st), n, int(n_m), float(dt),
                                         float(rcrit_factor), ctypes.byref(o), _stream_handle(stream))
@@ -240,7 +248,7 @@ class Context:
         the accelerations at the current positions on entry and the new
         evaluation on return."""
         n = int(state["x"].numel())
-        _state_struct(state)  # the same checks as an evaluation's state
+        _state_struct(state, out)  # the same checks as an evaluation's state
         st = symba_mstate(*(state[k].data_ptr() for k in STATE_KEYS))
         o = out.c_struct()
         rc = lib().symba_step(self._h, ctypes.byref(st), n, int(n_m), float(h), float(rcrit_factor),
@@ -252,7 +260,7 @@ class Context:
         """symba_step_batch: problems = list of (device state, n_m, h, rcrit_factor, Outputs)."""
         arr = (symba_step_problem * len(problems))()
         for k, (state, n_m, h, f, out) in enumerate(problems):
-            _state_struct(state)
+            _state_struct(state, out)
             arr[k].state = symba_mstate(*(state[key].data_ptr() for key in STATE_KEYS))
             arr[k].n = int(state["x"].numel())
             arr[k].n_m = int(n_m)
@@ -269,7 +277,7 @@ class Context:
         n = int(state["x"].numel())
         if out is None:
             out = Outputs(n, min(self.max_pairs, max(4 * n, 4096)), device=state["x"].device)
-        st = _state_struct(state)
+        st = _state_struct(state, out)
         o = out.c_struct()
         rows = ctypes.c_int32(0)
         rc = lib().symba_autotune(self._h, ctypes.byref(st), n, int(n_m), float(dt), float(rcrit_factor),
@@ -281,7 +289,7 @@ class Context:
         """problems: list of (state, n_m, dt, rcrit_factor, Outputs)."""
         arr = (symba_problem * len(problems))()
         for k, (state, n_m, dt, f, out) in enumerate(problems):
-            arr[k].state = _state_struct(state)
+            arr[k].state = _state_struct(state, out)
             arr[k].n = int(state["x"].numel())
             arr[k].n_m = int(n_m)
             arr[k].dt = float(dt)

@@ -164,3 +164,19 @@ def test_binding_constants_match_header():
     for name in ("OPT_TILE_ROWS", "OPT_FIELD_ROWS", "OPT_SCREEN", "OPT_TIMING", "OPT_BIN", "OPT_ACC", "OPT_SPLIT",
                  "SCREEN_AUTO", "SCREEN_FP32", "SCREEN_FP64", "ACC_INTERACTION", "ACC_HELIO"):
         assert getattr(B, name) == defs[name], name
+
+
+def test_binding_rejects_mismatched_sizes():
+    """The binding refuses, before anything reaches the library, a state
+    whose arrays differ in length and outputs smaller than the state (the
+    library takes every array to hold len(x) bodies)."""
+    import torch
+    s = {k: torch.zeros(10, dtype=torch.float64) for k in B.STATE_KEYS}
+    s["m"] = torch.zeros(9, dtype=torch.float64)
+    with pytest.raises(ValueError, match="elements"):
+        B._state_struct(s)
+    s["m"] = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="outputs hold"):
+        B._state_struct(s, B.Outputs(8, 16, device="cpu"))
+    with pytest.raises(ValueError, match="device tensor"):   # host tensors never reach the library
+        B._state_struct(s, B.Outputs(10, 16, device="cpu"))
