@@ -22,6 +22,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -52,15 +53,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(n_tasks_per_launch_bytes=None):
+def traffic_from_profiles(workload, rows):
     """HBM bytes per tile-kernel launch from the committed rocprofv3 PMC summary,
-    only if it was taken on the current kernel source."""
+    only if it was taken on the current kernel source, for this workload and
+    with the tile size this run uses."""
+    if workload != "disk10k":
+        return None
     p = os.path.join(ROOT, "profiles", "traffic_k_tiles_disk10k.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
     if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    m = re.search(r"k_tiles<(\d+)", t.get("kernel", ""))
+    if not m or int(m.group(1)) != rows:
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -241,7 +248,7 @@ def main():
                    "plan": dict(zip(("rows", "split"), plan))},
         "latency_ms": latency,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic_from_profiles(),
+                     "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic_from_profiles(args.workload, plan[0]),
                      "kernel": "k_tiles", "kernel_us": tile_ms * 1e3, "flop_per_launch": flop},
         "batched": batched,
         "served": served,
