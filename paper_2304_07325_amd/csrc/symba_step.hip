@@ -69,19 +69,40 @@ __device__ __forceinline__ void read_momentum(const StepDesc &s, const double *p
     pz = block_sum(c, red);
 }
 
+// Coefficients of the Stumpff series: 1/(2k+2)! and 1/(2k+3)!, k = 0 ..
+// kStumpffTerms - 1, computed at compile time.  For |x| < 1 the first
+// omitted terms, 1/24! and 1/25!, are below 2^-53 of c2 and c3.
+constexpr int kStumpffTerms = 11;
+struct StumpffCoeffs {
+    double c2[kStumpffTerms], c3[kStumpffTerms];
+};
+constexpr StumpffCoeffs make_stumpff_coeffs() {
+    StumpffCoeffs t{};
+    double f = 2.0;  // (2k+2)!
+    for (int k = 0; k < kStumpffTerms; ++k) {
+        t.c2[k] = 1.0 / f;
+        f *= 2.0 * k + 3.0;
+        t.c3[k] = 1.0 / f;
+        f *= 2.0 * k + 4.0;
+    }
+    return t;
+}
+constexpr StumpffCoeffs kStumpff = make_stumpff_coeffs();
+
 // Stumpff functions c0..c3 of x (Danby, Fundamentals of Celestial Mechanics,
 // Sec. 6.9): c0 = cos sqrt x, c1 = sin sqrt x / sqrt x, c2 = (1 - cos sqrt x) / x,
 // c3 = (sqrt x - sin sqrt x) / sqrt(x)^3, continued through x <= 0.  Near 0
-// the series of c2 and c3 (terms (-x)^k / (2k+2)! and (-x)^k / (2k+3)!),
-// then c0 = 1 - x c2 and c1 = 1 - x c3.
+// the series of c2 and c3 (terms (-x)^k / (2k+2)! and (-x)^k / (2k+3)!) in
+// Horner form, one FMA per term with no division on the solver's critical
+// path, then c0 = 1 - x c2 and c1 = 1 - x c3.
 __device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double &c2, double &c3) {
     if (fabs(x) < 1.0) {
-        double t2 = 1.0 / 2.0, t3 = 1.0 / 6.0, s2 = t2, s3 = t3;
-        for (int k = 1; k <= 12; ++k) {
-            t2 *= -x / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
-            t3 *= -x / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
-            s2 += t2;
-            s3 += t3;
+        const double y = -x;
+        double s2 = kStumpff.c2[kStumpffTerms - 1], s3 = kStumpff.c3[kStumpffTerms - 1];
+#pragma unroll
+        for (int k = kStumpffTerms - 2; k >= 0; --k) {
+            s2 = __builtin_fma(s2, y, kStumpff.c2[k]);
+            s3 = __builtin_fma(s3, y, kStumpff.c3[k]);
         }
         c2 = s2;
         c3 = s3;
@@ -132,8 +153,9 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
     }
     stumpff(beta * s * s, c0, c1, c2, c3);
     const double r = r0 * c0 + s * (eta * c1 + s * c2);
-    const double f = 1.0 - s * s * c2 / r0, g = h - s * s * s * c3;
-    const double fd = -s * c1 / (r * r0), gd = 1.0 - s * s * c2 / r;
+    const double inv_r0 = 1.0 / r0, inv_r = 1.0 / r;
+    const double f = 1.0 - s * s * c2 * inv_r0, g = h - s * s * s * c3;
+    const double fd = -s * c1 * inv_r0 * inv_r, gd = 1.0 - s * s * c2 * inv_r;
     const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
     vx = fd * x + gd * vx;
     vy = fd * y + gd * vy;
