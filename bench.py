@@ -377,14 +377,15 @@ def bench_step(args, B, dg, torch):
 
 
 def bench_other_workloads(args, B, dg, torch):
-    """The 1k disk, the 100k-body field disk (1000 massive) and the 50k-body
-    hot disk: throughput over their Kepler-advanced states, and for the hot
+    """The paper's other benchmark sizes (1k, 2k and 5k cold disks), the
+    100k-body field disk (1000 massive) and the 50k-body hot disk: throughput
+    over their Kepler-advanced states, and for the hot
     disk the screen's candidates vs confirmed pairs and one evaluation checked
     against the oracle (every pair and label, 600 sampled accelerations)."""
     import numpy as np
     res = {}
     dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
-    for name in ("disk1k", "field100k", "hot50k"):
+    for name in ("disk1k", "disk2k", "disk5k", "field100k", "hot50k"):
         w = dg.WORKLOADS[name]
         n, n_m, evals = w["n"], w["n_massive"], w["evals"]
         disk = dg.make_disk(n, n_m, w["kind"], w["seed"])

@@ -212,6 +212,8 @@ RCRIT_FACTOR = 3.0      # critical radius in Hill radii
 
 WORKLOADS = {
     "disk1k": dict(n=1000, n_massive=999, kind="cold", evals=20, seed=1001),
+    "disk2k": dict(n=2000, n_massive=1999, kind="cold", evals=20, seed=1010),
+    "disk5k": dict(n=5000, n_massive=4999, kind="cold", evals=20, seed=1011),
     "disk10k": dict(n=10000, n_massive=9999, kind="cold", evals=100, seed=1002),
     "field100k": dict(n=100000, n_massive=1000, kind="cold", evals=100, seed=1003),
     "hot50k": dict(n=50000, n_massive=49999, kind="hot", evals=10, seed=1004),

@@ -92,4 +92,7 @@ def test_generator_matches_paper_parameters():
     assert np.allclose(d.m, acc["mass_earth"] * dg.M_EARTH)
     assert d.dt == acc["time_step_years"] * dg.YEAR
     w = dg.WORKLOADS
-    assert w["disk1k"]["n"] in p["benchmark_N"] and w["disk10k"]["n"] in p["benchmark_N"]
+    # the paper's benchmark sizes (Sec. 3), all-massive cold disks
+    assert sorted(w[k]["n"] for k in ("disk1k", "disk2k", "disk5k", "disk10k")) == sorted(p["benchmark_N"])
+    for k in ("disk1k", "disk2k", "disk5k", "disk10k"):
+        assert w[k]["kind"] == "cold" and w[k]["n_massive"] == w[k]["n"] - 1
