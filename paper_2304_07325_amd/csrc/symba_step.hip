@@ -39,14 +39,15 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return t;
 }
 
-// This block's share of P = sum m_i v_i over the massive bodies [0, n_tri).
+// This block's share of P = sum m_i v_i over the massive bodies [0, n_tri),
+// written to the launch's partials and returned to every thread.
 __device__ __forceinline__ void write_momentum(const StepDesc &s, double *part, int64_t k, double vx, double vy,
-                                               double vz) {
+                                               double vz, double &px, double &py, double &pz) {
     __shared__ double red[kStepWaves];
     const double m = k < s.n_tri ? s.m[k] : 0.0;
-    const double px = block_sum(m * vx, red);
-    const double py = block_sum(m * vy, red);
-    const double pz = block_sum(m * vz, red);
+    px = block_sum(m * vx, red);
+    py = block_sum(m * vy, red);
+    pz = block_sum(m * vz, red);
     if (threadIdx.x == 0) {
         part[3 * blockIdx.x] = px;
         part[3 * blockIdx.x + 1] = py;
@@ -185,8 +186,8 @@ __device__ __forceinline__ int64_t body_of(const StepDesc &s) {
     return ((int64_t)blockIdx.x - s.blk_base) * kStepThreads + threadIdx.x;
 }
 
-// v += kick_h a, then this block's momentum partial sum.
-__device__ __forceinline__ void kick_momentum(const StepDesc &s) {
+// v += kick_h a, then this block's momentum partial sum (returned in p*).
+__device__ __forceinline__ void kick_momentum(const StepDesc &s, double &px, double &py, double &pz) {
     const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (k < s.n) {
@@ -197,13 +198,12 @@ __device__ __forceinline__ void kick_momentum(const StepDesc &s) {
         s.vy[k] = vy;
         s.vz[k] = vz;
     }
-    write_momentum(s, s.mom0, k, vx, vy, vz);
+    write_momentum(s, s.mom0, k, vx, vy, vz, px, py, pz);
 }
 
-// x += sun_h P, Kepler drift for kepler_h, then the new momentum partial sum.
-__device__ __forceinline__ void sun_kepler(const StepDesc &s) {
-    double px, py, pz;
-    read_momentum(s, s.mom0, px, py, pz);
+// x += sun_h P (P = p* on entry), Kepler drift for kepler_h, then the new
+// momentum partial sum (returned in p*).
+__device__ __forceinline__ void sun_kepler(const StepDesc &s, double &px, double &py, double &pz) {
     const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (k < s.n) {
@@ -219,13 +219,11 @@ __device__ __forceinline__ void sun_kepler(const StepDesc &s) {
         s.vy[k] = vy;
         s.vz[k] = vz;
     }
-    write_momentum(s, s.mom1, k, vx, vy, vz);
+    write_momentum(s, s.mom1, k, vx, vy, vz, px, py, pz);
 }
 
 // x += sun_h P with the momentum after the Kepler drift.
-__device__ __forceinline__ void sun(const StepDesc &s) {
-    double px, py, pz;
-    read_momentum(s, s.mom1, px, py, pz);
+__device__ __forceinline__ void sun(const StepDesc &s, double px, double py, double pz) {
     const int64_t k = body_of(s);
     if (k < s.n) {
         s.x[k] += s.sun_h * px;
@@ -237,30 +235,36 @@ __device__ __forceinline__ void sun(const StepDesc &s) {
 template <bool LIST>
 __global__ __launch_bounds__(kStepThreads) void k_kick_momentum(const StepDesc one, const StepDesc *list,
                                                                 int n_list) {
-    kick_momentum(problem<LIST>(one, list, n_list));
+    double px, py, pz;
+    kick_momentum(problem<LIST>(one, list, n_list), px, py, pz);
 }
 
 template <bool LIST>
 __global__ __launch_bounds__(kStepThreads) void k_sun_kepler(const StepDesc one, const StepDesc *list,
                                                              int n_list) {
-    sun_kepler(problem<LIST>(one, list, n_list));
+    const StepDesc &s = problem<LIST>(one, list, n_list);
+    double px, py, pz;
+    read_momentum(s, s.mom0, px, py, pz);
+    sun_kepler(s, px, py, pz);
 }
 
 template <bool LIST>
 __global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const StepDesc *list, int n_list) {
-    sun(problem<LIST>(one, list, n_list));
+    const StepDesc &s = problem<LIST>(one, list, n_list);
+    double px, py, pz;
+    read_momentum(s, s.mom1, px, py, pz);
+    sun(s, px, py, pz);
 }
 
-// All three for a problem of one block (n <= kStepThreads): the same code in
-// one launch, the block's barriers standing in for the launch boundaries (a
-// thread reads back only its own body, and the momentum partial it reads was
-// written by this block), so the bits are those of the three launches.
+// All three for a problem of one block (n <= kStepThreads), in one launch:
+// each thread reads back only its own body, and the momentum is the block's
+// own sum, which is exactly what reading back the one partial would give
+// (that sum plus zeros), so the bits are those of the three launches.
 __global__ __launch_bounds__(kStepThreads) void k_drifts_block(const StepDesc one) {
-    kick_momentum(one);
-    __syncthreads();
-    sun_kepler(one);
-    __syncthreads();
-    sun(one);
+    double px, py, pz;
+    kick_momentum(one, px, py, pz);
+    sun_kepler(one, px, py, pz);
+    sun(one, px, py, pz);
 }
 
 }  // namespace
