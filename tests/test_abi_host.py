@@ -180,3 +180,12 @@ def test_binding_rejects_mismatched_sizes():
         B._state_struct(s, B.Outputs(8, 16, device="cpu"))
     with pytest.raises(ValueError, match="device tensor"):   # host tensors never reach the library
         B._state_struct(s, B.Outputs(10, 16, device="cpu"))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits at once with a message."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
