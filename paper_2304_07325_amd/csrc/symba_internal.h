@@ -16,8 +16,10 @@ constexpr int kGatherWaves = 4;    // tiles per block of the tile-box kernel
 constexpr int kBinTempInts = 2 * 2048 + 2 * 2048 + 2 * 2049;  // cell counts, fills, starts
 
 // Per-problem device counters (zero between calls).
-constexpr int kCtrPairs = 0;   // flagged pairs found
-constexpr int kCtrStatus = 3;  // status bits (slots 1 and 2 are unused)
+constexpr int kCtrPairs = 0;   // flagged pairs found (appended to by the tile kernel)
+constexpr int kCtrFound = 1;   // the final count, published by the final kernel for the closing kernel
+                               // (written every call, never reset: see close_block)
+constexpr int kCtrStatus = 3;  // status bits (slot 2 is unused)
 constexpr int kCtrSlots = 4;
 
 // Context-wide statistics accumulated over calls (read by symba_read_stats).
@@ -75,7 +77,7 @@ struct Desc {
     int32_t *bcnt;        // [nb] flagged pairs per bucket, zero between calls
     int32_t *bfill;       // [nb] bucket fill counters, zero between calls
     int32_t nb;           // buckets: min(n, kMaxBuckets)
-    unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls
+    unsigned long long *ctr;  // [kCtrSlots] counters, zero between calls (kCtrFound excepted)
     unsigned long long *stats;  // [kStatSlots] context-wide statistics
     // binning scratch (written by the binning kernels); null when not binned
     int32_t *bin_key;     // [n] grid cell of each body

@@ -1347,6 +1347,10 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
         // per block on a shared counter would serialise (~12 ns each)
         d.blk_groups[lb] = groups;
         if (bad) atomicOr(d.ctr + kCtrStatus, kStatusNonfinite);
+        // the pair count for every closing block, in a slot that the closing
+        // kernel never resets (its block 0 resets the live counter, which the
+        // other closing blocks therefore must not read)
+        if (lb == 0) d.ctr[kCtrFound] = d.ctr[kCtrPairs];
     }
 }
 
@@ -1419,7 +1423,10 @@ __device__ __forceinline__ void close_block(const Desc &d, int c, int blocks) {
     // address whether or not it holds a pair), saving a round trip
     int4 first = make_int4(0, 0, 0, 0);
     if (s0 < d.pair_scratch_cap) first = d.sorted[s0];
-    const int64_t found = (int64_t)d.ctr[kCtrPairs];
+    // the count as the final kernel published it: block 0 below resets the
+    // live counter (kCtrPairs) while other blocks may still be starting, so
+    // no block reads that one here
+    const int64_t found = (int64_t)d.ctr[kCtrFound];
     const int64_t cap = d.pair_cap < d.pair_scratch_cap ? d.pair_cap : d.pair_scratch_cap;
     const bool fits = found <= cap;
     const int64_t stride = (int64_t)blocks * kFinalizeThreads;
@@ -1464,7 +1471,10 @@ __device__ __forceinline__ void close_block(const Desc &d, int c, int blocks) {
         *d.n_pairs_out = found;
         *d.n_groups_out = groups;
         *d.status_out = (int32_t)(d.ctr[kCtrStatus] | (fits ? 0ull : kStatusCapacity));
-        for (int k = 0; k < kCtrSlots; ++k) d.ctr[k] = 0;
+        // only block 0 reads the status word, and no closing block reads the
+        // live pair counter, so these resets race with nothing
+        d.ctr[kCtrPairs] = 0;
+        d.ctr[kCtrStatus] = 0;
     }
 }
 
