@@ -1,7 +1,8 @@
 """Oracle for the SyMBA kick/encounter step -- test infrastructure only.
 
 Python front end (ctypes) of the plain single-threaded FP64 C oracle in
-symba_oracle.c.  Only the tests, the smoke check and the benchmark's
+symba_oracle.c, and of its all-core build (symba_oracle_omp.c), which the
+benchmark times for context.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the GPU library and its binding never do.
 
 Every function takes host numpy arrays (float64 SoA, int32 pair lists) and
@@ -22,9 +23,22 @@ SRC_PATH = os.path.join(_HERE, "symba_oracle.c")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-mfma", "-fno-fast-math", "-fPIC", "-shared"]
 
 
+OMP_LIB_PATH = os.path.join(_HERE, "libsymba_oracle_omp.so")
+OMP_SRC_PATH = os.path.join(_HERE, "symba_oracle_omp.c")
+
+
 def build(out_path: str = LIB_PATH, src_path: str = SRC_PATH, extra=()) -> str:
-    """Compile the oracle with gcc (FP contraction off; fma() is explicit)."""
+    """Compile the oracle with gcc (FP contraction off; fma() is explicit),
+    and its all-core build (OpenMP) for the benchmark's CPU context."""
     cmd = ["gcc", *CFLAGS, *extra, "-o", out_path, src_path, "-lm"]
+    subprocess.run(cmd, check=True)
+    if out_path == LIB_PATH:
+        build_omp()
+    return out_path
+
+
+def build_omp(out_path: str = OMP_LIB_PATH) -> str:
+    cmd = ["gcc", *CFLAGS, "-fopenmp", "-o", out_path, OMP_SRC_PATH, SRC_PATH, "-lm"]
     subprocess.run(cmd, check=True)
     return out_path
 
@@ -55,6 +69,18 @@ def _declare(lib):
     lib.oracle_helio.restype = ctypes.c_int
     lib.oracle_helio.argtypes = [_I64, _I64] + [_P] * 10
     return lib
+
+
+def load_omp(path: str = OMP_LIB_PATH):
+    """The all-core build (OpenMP; the paper's Sec. 2 scheme), compiled first
+    only if it is not built."""
+    if not os.path.exists(path):
+        build_omp(path)
+    L = _declare(ctypes.CDLL(path))
+    L.oracle_kick_encounter_omp.restype = _I64
+    L.oracle_kick_encounter_omp.argtypes = ([_I64, _I64] + [_P] * 8 + [_D, _D] + [_P] * 5
+                                            + [_I64, _P, _P, _P])
+    return L
 
 
 def load(path: str = LIB_PATH):
@@ -182,6 +208,34 @@ class Oracle:
             if cnt <= cap:
                 return dict(acc=np.stack(acc, axis=1), pair_i=pi[:cnt].copy(),
                             pair_j=pj[:cnt].copy(), group_id=gid, n_groups=int(ng.value))
+            cap = int(cnt)
+
+    def kick_encounter_omp(self, s, n_m, dt, f, cap=None):
+        """The whole step on every core (needs the library from load_omp()):
+        the paper's Sec. 2 scheme, thread-private accumulators summed in
+        thread order.  Returns kick_encounter's dict plus `threads`."""
+        arrs = [_f64(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "m", "rh")]
+        n = arrs[0][0].size
+        if cap is None:
+            cap = max(4 * n, 4096)
+        while True:
+            acc = [np.zeros(n) for _ in range(3)]
+            pi = np.zeros(cap, np.int32)
+            pj = np.zeros(cap, np.int32)
+            gid = np.zeros(n, np.int32)
+            ng = ctypes.c_int64(0)
+            th = ctypes.c_int32(0)
+            cnt = self.L.oracle_kick_encounter_omp(
+                n, n_m, *(a[1] for a in arrs), float(dt), float(f),
+                *(a.ctypes.data for a in acc), pi.ctypes.data, pj.ctypes.data, cap,
+                gid.ctypes.data, ctypes.addressof(ng), ctypes.addressof(th))
+            if cnt == -1:
+                raise ValueError("oracle_kick_encounter_omp: invalid arguments")
+            if cnt < 0:
+                raise MemoryError("oracle_kick_encounter_omp: out of host memory")
+            if cnt <= cap:
+                return dict(acc=np.stack(acc, axis=1), pair_i=pi[:cnt].copy(), pair_j=pj[:cnt].copy(),
+                            group_id=gid, n_groups=int(ng.value), threads=int(th.value))
             cap = int(cnt)
 
     def helio(self, s, n_m, acc):

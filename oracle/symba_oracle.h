@@ -92,6 +92,21 @@ int oracle_helio(int64_t n, int64_t n_m,
                  const double *ax, const double *ay, const double *az,
                  double *hx, double *hy, double *hz);
 
+/* All-core build (symba_oracle_omp.c, OpenMP; the benchmark's CPU context):
+ * oracle_kick_encounter computed with the paper's Sec. 2 scheme -- rows
+ * folded so that every thread gets the same number of pairs, thread-private
+ * accumulators summed in thread order.  Pairs and groups equal the
+ * single-thread oracle's; accelerations differ by the order of additions.
+ * *threads_used = the OpenMP thread count.  Returns as
+ * oracle_kick_encounter, or -2 when host memory runs out. */
+int64_t oracle_kick_encounter_omp(int64_t n, int64_t n_m,
+                                  const double *x, const double *y, const double *z,
+                                  const double *vx, const double *vy, const double *vz,
+                                  const double *m, const double *rh, double dt, double rcrit_factor,
+                                  double *ax, double *ay, double *az,
+                                  int32_t *pair_i, int32_t *pair_j, int64_t cap,
+                                  int32_t *group_id, int64_t *n_groups, int32_t *threads_used);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,9 @@ FLAGS = [
 
 
 def build(verbose: bool = False, extra=()) -> str:
+    # a failed build must not leave an older library behind to be loaded
+    if os.path.exists(LIB):
+        os.remove(LIB)
     cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", *SOURCES, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -64,13 +64,15 @@ constexpr int kTaskThreads = kTaskWaves * kWave;
 constexpr int kSteps = kWave / kTaskWaves;     // steps of each 64-step tile per wave
 
 // Workgroup LDS of a task: the streamed block (RS tiles of 64 bodies, each
-// stored twice, 16-byte pairs); after the passes the same space holds the
-// waves' partial sums [side: stationary, streamed][wave][slot][component][lane].
+// stored twice, 16-byte pairs) and the stationary block (RS tiles, read into
+// registers once the block is staged); after the passes the same space holds
+// the waves' partial sums [side: stationary, streamed][wave][slot][component][lane].
 template <int RS>
 struct __align__(16) TaskLds {
     union {
         struct {
             double2 xy[RS][2 * kWave], zm[RS][2 * kWave], vxy[RS][2 * kWave], vzq[RS][2 * kWave];
+            double2 sxy[RS * kWave], szm[RS * kWave], svxy[RS * kWave], svzq[RS * kWave];
         } tile;
         double comb[2][kTaskWaves][RS][3][kWave];
     };
@@ -337,24 +339,48 @@ struct Body {
     double x, y, z, m, vx, vy, vz, Q;
 };
 
-template <bool REG, bool F32>
-__device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
-    Body b;
+// The inputs of one body as read from memory, held in registers until the
+// task's staging.  Entries past the end of their segment are padding: far
+// away (x = 2^300, beyond every valid position), massless and at rest.
+struct Raw {
+    double x, y, z, m, vx, vy, vz, rh;
+};
+
+__device__ __forceinline__ Raw load_raw(const Desc &d, int64_t k, int64_t limit) {
+    Raw r;
     if (k < limit) {
-        b.x = d.bx[k];
-        b.y = d.by[k];
-        b.z = d.bz[k];
-        b.m = d.bm[k];
-        const double vx = d.bvx[k], vy = d.bvy[k], vz = d.bvz[k];
-        const double rc = d.f * d.brh[k];
+        r.x = d.bx[k];
+        r.y = d.by[k];
+        r.z = d.bz[k];
+        r.m = d.bm[k];
+        r.vx = d.bvx[k];
+        r.vy = d.bvy[k];
+        r.vz = d.bvz[k];
+        r.rh = d.brh[k];
+    } else {
+        r.x = kPadPos;
+        r.y = r.z = r.m = r.vx = r.vy = r.vz = r.rh = 0.0;
+    }
+    return r;
+}
+
+template <bool REG, bool F32>
+__device__ __forceinline__ Body body_of(const Desc &d, const Raw &r) {
+    Body b;
+    if (r.x != kPadPos) {
+        b.x = r.x;
+        b.y = r.y;
+        b.z = r.z;
+        b.m = r.m;
+        const double rc = d.f * r.rh;
         const double D = d.screen_dt2;
-        const double v2 = __builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx));
+        const double v2 = __builtin_fma(r.vz, r.vz, __builtin_fma(r.vy, r.vy, r.vx * r.vx));
         b.Q = kScreenInflate * __builtin_fma(D, v2, kScreenQ * (rc * rc));
         const double s = REG ? -2.0 * D : 1.0;
-        b.vx = s * vx;
-        b.vy = s * vy;
-        b.vz = s * vz;
-    } else {  // padding: far away, massless, at rest
+        b.vx = s * r.vx;
+        b.vy = s * r.vy;
+        b.vz = s * r.vz;
+    } else {  // padding
         b.x = kPadPos;
         b.y = b.z = b.m = b.vx = b.vy = b.vz = b.Q = 0.0;
     }
@@ -367,12 +393,17 @@ __device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limi
     return b;
 }
 
+template <bool REG, bool F32>
+__device__ __forceinline__ Body load_body(const Desc &d, int64_t k, int64_t limit) {
+    return body_of<REG, F32>(d, load_raw(d, k, limit));
+}
+
 // Stage bodies [j0, j0 + 64 nq) (entries past `limit` become padding) into
 // tiles 0..nq-1 of the workgroup's LDS, each entry also at +64.  All threads
 // of the workgroup take part; the caller brackets it with barriers.
 template <int RS, bool F32>
 __device__ __forceinline__ void stage(const Desc &d, TaskLds<RS> &L, int64_t j0, int nq, int64_t limit) {
-    for (int e = threadIdx.x; e < nq * kWave; e += kTaskThreads) {
+    for (int e = (int)threadIdx.x; e < nq * kWave; e += kTaskThreads) {
         const Body b = load_body<false, F32>(d, j0 + e, limit);
         const int q = e / kWave, jj = e % kWave;
         L.tile.xy[q][jj] = L.tile.xy[q][jj + kWave] = make_double2(b.x, b.y);
@@ -607,7 +638,7 @@ __device__ __forceinline__ void write_sums(const Desc &d, TaskLds<RS> &L, const 
         L.comb[1][w][r][2][jend] = aj[r][2];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 2 * NR * kWave; e += kTaskThreads) {
+    for (int e = (int)threadIdx.x; e < 2 * NR * kWave; e += kTaskThreads) {
         const int side = e / (NR * kWave), idx = e % (NR * kWave), r = idx / kWave, ll = idx % kWave;
         if (diag && side == 1) continue;
         double sum[3];
@@ -626,86 +657,172 @@ __device__ __forceinline__ void write_sums(const Desc &d, TaskLds<RS> &L, const 
     }
 }
 
-// Block pair (I, J) of the folded triangle, by the four waves of the
-// workgroup.  Partial sums land in slot J for the stationary bodies of block
-// I and in slot I for the bodies of block J (slot I for both when I == J).
-// BIN: the problem is binned, so tile pairs that cannot meet run screen-free.
-// F32: the pair screen runs in FP32 (screen32).
-template <int R, int RS, bool BIN, bool F32>
-__device__ __forceinline__ void triangle_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t I,
-                                              int64_t J) {
-    const int l = lane(), w = wave_id();
-    const int t0 = w * kSteps;
-    const int64_t ib = I * R * kWave, jb = J * R * kWave;
-    Slots<R> S;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        S.b[r] = load_body<true, F32>(d, ib + r * kWave + l, d.n_tri);
-        S.ax[r] = S.ay[r] = S.az[r] = 0.0;
+// A task of the tile kernel, decoded from its index in the problem's task
+// list: a whole block pair (I, J) of the folded triangle, a tile pair of a
+// split diagonal, or a field block against every massive row.
+struct TaskInfo {
+    int kind;                 // kTaskWhole, kTaskSplit or kTaskField
+    int nq, nstat;            // streamed and stationary tiles
+    int r, q;                 // split: stationary tile of I, streamed tile of J
+    int64_t I, J;             // blocks of the pair
+    int64_t ib, jb;           // first stationary and first streamed body
+    int64_t slot_i, slot_j;   // split: partial slots of the stationary and the streamed side
+    int64_t fb;               // field: field block
+};
+
+constexpr int kTaskWhole = 0, kTaskSplit = 1, kTaskField = 2;
+
+template <int R>
+__device__ __forceinline__ TaskInfo decode_task(const Desc &d, int64_t lt) {
+    TaskInfo T;
+    T.r = T.q = 0;
+    T.I = T.J = T.ib = T.jb = T.slot_i = T.slot_j = T.fb = 0;
+    if (lt < d.n_whole) {
+        T.kind = kTaskWhole;
+        whole_decode(d.B, d.n_split, lt, T.I, T.J);
+        T.nq = T.nstat = R;
+        T.ib = T.I * R * kWave;
+        T.jb = T.J * R * kWave;
+    } else if (lt < d.n_tri_tasks) {
+        T.kind = kTaskSplit;
+        const SplitTask S = split_decode(d.B, R, lt - d.n_whole);
+        T.nq = T.nstat = 1;
+        T.r = S.r;
+        T.q = S.q;
+        T.I = S.I;
+        T.J = S.J;
+        T.ib = (S.I * R + S.r) * kWave;
+        T.jb = (S.J * R + S.q) * kWave;
+        T.slot_i = S.slot_i;
+        T.slot_j = S.slot_j;
+    } else {
+        T.kind = kTaskField;
+        T.nq = T.nstat = 0;
+        T.fb = lt - d.n_tri_tasks;
     }
-    // lane r R + q decides stationary tile r against streamed tile q (the box
-    // loads overlap the body loads); bit q of free_q: screen-free tile q
-    unsigned free_q = 0;
-    if (BIN && I != J) {
-        const bool apart = l >= R * R || tiles_apart(d, tri_box(d, I * R + l / R), tri_box(d, J * R + l % R));
-        const unsigned long long m = __ballot(apart);
+    return T;
+}
+
+// Bodies a triangle task reads, one list per workgroup: its streamed tiles
+// (entries [0, 64 nq)) then its stationary tiles; thread t takes entries t
+// and t + 256, so every body is read from memory once per task.  PF entries
+// per thread cover the largest task (2 R 64 bodies).
+template <int R>
+constexpr int body_slots() { return R == 4 ? 2 : 1; }
+
+template <int PF>
+__device__ __forceinline__ void load_task_bodies(const Desc &d, const TaskInfo &T, Raw (&pf)[PF]) {
+    if (T.kind == kTaskField) return;
+    const int nstr = T.nq * kWave, nstat = T.nstat * kWave;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            bool all = true;
+    for (int p = 0; p < PF; ++p) {
+        const int k = (int)threadIdx.x + p * kTaskThreads;
+        if (k < nstr)
+            pf[p] = load_raw(d, T.jb + k, d.n_tri);
+        else if (k - nstr < nstat)
+            pf[p] = load_raw(d, T.ib + (k - nstr), d.n_tri);
+    }
+}
+
+// The loaded bodies of a triangle task into LDS: streamed ones in their
+// screen form for the LDS side (each entry also at +64), stationary ones in
+// the form for the register side (each of the four waves then reads them
+// into registers).  Every thread of the workgroup takes part; the caller
+// brackets it with barriers.
+template <int RS, bool F32, int PF>
+__device__ __forceinline__ void stage_loaded(const Desc &d, TaskLds<RS> &L, const TaskInfo &T,
+                                                 const Raw (&pf)[PF]) {
+    const int nstr = T.nq * kWave, nstat = T.nstat * kWave;
 #pragma unroll
-            for (int r = 0; r < R; ++r) all = all && ((m >> (r * R + q)) & 1ull);
-            free_q |= (all ? 1u : 0u) << q;
+    for (int p = 0; p < PF; ++p) {
+        const int k = (int)threadIdx.x + p * kTaskThreads;
+        if (k < nstr) {
+            const Body b = body_of<false, F32>(d, pf[p]);
+            const int q = k / kWave, jj = k % kWave;
+            L.tile.xy[q][jj] = L.tile.xy[q][jj + kWave] = make_double2(b.x, b.y);
+            L.tile.zm[q][jj] = L.tile.zm[q][jj + kWave] = make_double2(b.z, b.m);
+            L.tile.vxy[q][jj] = L.tile.vxy[q][jj + kWave] = make_double2(b.vx, b.vy);
+            L.tile.vzq[q][jj] = L.tile.vzq[q][jj + kWave] = make_double2(b.vz, b.Q);
+        } else if (k - nstr < nstat) {
+            const Body b = body_of<true, F32>(d, pf[p]);
+            const int e = k - nstr;
+            L.tile.sxy[e] = make_double2(b.x, b.y);
+            L.tile.szm[e] = make_double2(b.z, b.m);
+            L.tile.svxy[e] = make_double2(b.vx, b.vy);
+            L.tile.svzq[e] = make_double2(b.vz, b.Q);
         }
     }
-    stage<RS, F32>(d, L, jb, R, d.n_tri);
-    __syncthreads();
+}
+
+// Stationary body e of the staged block, as the lane keeps it in registers.
+template <int RS>
+__device__ __forceinline__ Body stationary_body(const TaskLds<RS> &L, int e) {
+    const double2 a = L.tile.sxy[e], b = L.tile.szm[e], c = L.tile.svxy[e], f = L.tile.svzq[e];
+    return Body{a.x, a.y, b.x, b.y, c.x, c.y, f.x, f.y};
+}
+
+// Tile pairs of a whole block pair that cannot produce a candidate (binned
+// problems only): lane r R + q decides stationary tile r against streamed
+// tile q; bit q of the result is set when tile q is apart from every
+// stationary tile.
+template <int R>
+__device__ __forceinline__ unsigned whole_free_tiles(const Desc &d, const TaskInfo &T) {
+    const int l = lane();
+    const bool apart = l >= R * R || tiles_apart(d, tri_box(d, T.I * R + l / R), tri_box(d, T.J * R + l % R));
+    const unsigned long long m = __ballot(apart);
+    unsigned free_q = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        bool all = true;
+#pragma unroll
+        for (int r = 0; r < R; ++r) all = all && ((m >> (r * R + q)) & 1ull);
+        free_q |= (all ? 1u : 0u) << q;
+    }
+    return free_q;
+}
+
+// Block pair (I, J) of the folded triangle, by the four waves of the
+// workgroup, once its blocks are staged and the stationary bodies are in S.
+// Partial sums land in slot J for the stationary bodies of block I and in
+// slot I for the bodies of block J (slot I for both when I == J).  BIN: the
+// problem is binned, so tile pairs that cannot meet run screen-free (bit q of
+// free_q).  F32: the pair screen runs in FP32 (screen32).
+template <int R, int RS, bool BIN, bool F32>
+__device__ __forceinline__ void whole_pair(const Desc &d, TaskLds<RS> &L, Queue &Q, const TaskInfo &T,
+                                           Slots<R> &S, unsigned free_q) {
+    const int t0 = wave_id() * kSteps;
     double aj[R][3];
-    if (I != J) {
+    if (T.I != T.J) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (BIN && ((free_q >> q) & 1u))
-                rotation_range<R, RS, R, !BIN, F32>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
-                                               aj[q][2]);
+                rotation_range<R, RS, R, !BIN, F32>(d, L, q, S, T.ib, T.jb + q * kWave, t0, Q, aj[q][0],
+                                                    aj[q][1], aj[q][2]);
             else
-                rotation_range<R, RS, R, true, F32>(d, L, q, S, ib, jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
-                                               aj[q][2]);
+                rotation_range<R, RS, R, true, F32>(d, L, q, S, T.ib, T.jb + q * kWave, t0, Q, aj[q][0], aj[q][1],
+                                                    aj[q][2]);
         }
     } else {
-        diagonal_tiles<R, RS, 0, F32>(d, L, S, ib, t0, Q, aj);
+        diagonal_tiles<R, RS, 0, F32>(d, L, S, T.ib, t0, Q, aj);
     }
     __syncthreads();  // every wave is done with the tiles
-    write_sums<R, RS, R>(d, L, S, aj, t0, I == J, J, ib, I, jb);
-    // The candidates left in this wave's queue are tested last, after the
-    // workgroup's barriers, so the other waves never wait on the test's
-    // memory round trips.
-    drain_rest(d, Q);
+    write_sums<R, RS, R>(d, L, S, aj, t0, T.I == T.J, T.J, T.ib, T.I, T.jb);
 }
 
 // Tile pair of a split diagonal (see split_decode): stationary tile r of
 // block I against streamed tile q of block J, both sides accumulated, by the
 // four waves of the workgroup as in a whole block pair.
 template <int R, int RS, bool BIN, bool F32>
-__device__ __forceinline__ void split_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t s) {
-    const int l = lane(), w = wave_id();
-    const int t0 = w * kSteps;
-    const SplitTask T = split_decode(d.B, R, s);
-    const int64_t ib = (T.I * R + T.r) * kWave, jb = (T.J * R + T.q) * kWave;
-    Slots<R> S;
-    S.b[0] = load_body<true, F32>(d, ib + l, d.n_tri);
-    S.ax[0] = S.ay[0] = S.az[0] = 0.0;
-    bool apart = false;
-    if (BIN) apart = __builtin_amdgcn_readfirstlane(
-                         tiles_apart(d, tri_box(d, T.I * R + T.r), tri_box(d, T.J * R + T.q)) ? 1 : 0) != 0;
-    stage<RS, F32>(d, L, jb, 1, d.n_tri);
-    __syncthreads();
+__device__ __forceinline__ void split_pair(const Desc &d, TaskLds<RS> &L, Queue &Q, const TaskInfo &T,
+                                           Slots<R> &S, bool apart) {
+    const int t0 = wave_id() * kSteps;
     double aj[R][3];
     if (BIN && apart)
-        rotation_range<R, RS, 1, !BIN, F32>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+        rotation_range<R, RS, 1, !BIN, F32>(d, L, 0, S, T.ib, T.jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
     else
-        rotation_range<R, RS, 1, true, F32>(d, L, 0, S, ib, jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
+        rotation_range<R, RS, 1, true, F32>(d, L, 0, S, T.ib, T.jb, t0, Q, aj[0][0], aj[0][1], aj[0][2]);
     __syncthreads();  // every wave is done with the tile
-    write_sums<R, RS, 1>(d, L, S, aj, t0, false, T.slot_i, ib, T.slot_j, jb);
-    drain_rest(d, Q);
+    write_sums<R, RS, 1>(d, L, S, aj, t0, false, T.slot_i, T.ib, T.slot_j, T.jb);
 }
 
 // This wave's 16 rows [t0, t0 + 16) of staged massive tile q against the
@@ -742,6 +859,7 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
 // Field block fb against every massive row, by the four waves of the
 // workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
 // pairs; the field accelerations are complete at the end and written directly.
+
 template <int RF, int RS, bool BIN, bool F32>
 __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb) {
     const int l = lane(), w = wave_id();
@@ -802,7 +920,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         L.comb[0][w][r][2][l] = az[r];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < RF * kWave; e += kTaskThreads) {
+    for (int e = (int)threadIdx.x; e < RF * kWave; e += kTaskThreads) {
         const int r = e / kWave, ll = e % kWave;
         const int64_t pos = f0 + e;
         if (pos >= d.n) continue;
@@ -818,7 +936,6 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         d.ay[k] = sum[1];
         d.az[k] = sum[2];
     }
-    drain_rest(d, Q);  // after the barriers, as in the triangle tasks
 }
 
 // Problem owning global index `key` of the task list (which 0), of the
@@ -838,12 +955,11 @@ __device__ inline int problem_of(const Desc *descs, int n_desc, int64_t key, int
     return lo;
 }
 
-template <int R, int RF, bool BIN, bool F32>
-__device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
-    constexpr int RS = R > RF ? R : RF;
-    // Without binning the tile kernel's inputs are the caller's arrays and no
-    // index map or box exists: said here at compile time, so that the unbinned
-    // kernel keeps no registers for them.
+// Without binning the tile kernel's inputs are the caller's arrays and no
+// index map or box exists: said here at compile time, so that the unbinned
+// kernel keeps no registers for them.
+template <bool BIN>
+__device__ __forceinline__ Desc tile_view(const Desc &desc) {
     Desc d = desc;
     if (!BIN) {
         d.bx = desc.x; d.by = desc.y; d.bz = desc.z; d.bm = desc.m;
@@ -851,26 +967,59 @@ __device__ __forceinline__ void run_task(const Desc &desc, int64_t t) {
         d.bidx = nullptr;
         d.tbox = nullptr;
     }
+    return d;
+}
+
+// One task per workgroup (the hardware dispatcher hands tasks to free
+// workgroup slots): the task's bodies are loaded once, each by one thread,
+// and staged in LDS, the stationary ones read back into registers.
+template <int R, int RF, bool BIN, bool F32>
+__device__ __forceinline__ void tile_task_once(const Desc &desc, int64_t t) {
+    constexpr int RS = R > RF ? R : RF;
+    constexpr int PF = body_slots<R>();
     __shared__ TaskLds<RS> L;
     __shared__ uint2 qbuf[kTaskWaves][queue_cap(RS)];
     Queue Q{qbuf[wave_id()], queue_cap(RS) - 1, 0, 0};
-    const int64_t lt = t - d.task_base;
-    if (lt < d.n_whole) {
-        int64_t I, J;
-        whole_decode(d.B, d.n_split, lt, I, J);
-        triangle_task<R, RS, BIN, F32>(d, L, Q, I, J);
-    } else if (lt < d.n_tri_tasks) {
-        split_task<R, RS, BIN, F32>(d, L, Q, lt - d.n_whole);
+    const Desc d = tile_view<BIN>(desc);
+    const TaskInfo T = decode_task<R>(d, t - d.task_base);
+    if (T.kind == kTaskField) {
+        field_task<RF, RS, BIN, F32>(d, L, Q, T.fb);
     } else {
-        field_task<RF, RS, BIN, F32>(d, L, Q, lt - d.n_tri_tasks);
+        Raw raw[PF];
+        load_task_bodies(d, T, raw);
+        unsigned free_q = 0;
+        bool apart = false;
+        if (BIN) {
+            if (T.kind == kTaskWhole) {
+                if (T.I != T.J) free_q = whole_free_tiles<R>(d, T);
+            } else {
+                apart = __builtin_amdgcn_readfirstlane(
+                            tiles_apart(d, tri_box(d, T.I * R + T.r), tri_box(d, T.J * R + T.q)) ? 1 : 0) != 0;
+            }
+        }
+        stage_loaded<RS, F32, PF>(d, L, T, raw);
+        __syncthreads();
+        Slots<R> S;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            S.b[r] = stationary_body<RS>(L, r * kWave + lane());
+            S.ax[r] = S.ay[r] = S.az[r] = 0.0;
+        }
+        if (T.kind == kTaskWhole)
+            whole_pair<R, RS, BIN, F32>(d, L, Q, T, S, free_q);
+        else
+            split_pair<R, RS, BIN, F32>(d, L, Q, T, S, apart);
     }
+    // the candidates left in this wave's queue are tested after the
+    // workgroup's barriers, so the other waves never wait on the test
+    drain_rest(d, Q);
 }
 
 // One problem: the descriptor is a kernel argument (scalar registers).
 template <int R, int RF, bool BIN, bool F32>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles(const Desc d) {
-    run_task<R, RF, BIN, F32>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
+    tile_task_once<R, RF, BIN, F32>(d, task_in_order(d.n_tri_tasks, d.n_tasks, blockIdx.x));
 }
 
 // Many problems of one tile size: every block finds its problem by the task
@@ -879,7 +1028,7 @@ template <int R, int RF, bool BIN, bool F32>
 __global__ __launch_bounds__(kTaskThreads) __attribute__((amdgpu_waves_per_eu(waves_per_eu(R))))
 void k_tiles_batch(const Desc *__restrict__ descs, int n_desc, int64_t task_begin) {
     const int64_t t = task_begin + blockIdx.x;
-    run_task<R, RF, BIN, F32>(descs[problem_of(descs, n_desc, t, 0)], t);
+    tile_task_once<R, RF, BIN, F32>(descs[problem_of(descs, n_desc, t, 0)], t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1535,6 +1684,7 @@ void launch_tiles_r(const TileGroup &g, const Desc &one, const Desc *descs, hipS
 }
 
 }  // namespace
+
 
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
                        int n_groups, int n_binned, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,
