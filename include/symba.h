@@ -173,16 +173,34 @@ int symba_set_option(symba_ctx *ctx, int option, int value);
  * the critical radius in Hill radii; out: caller-owned device outputs;
  * stream: a hipStream_t (NULL = default stream).  Enqueues the work and
  * returns without waiting; host-checkable faults return an error before
- * anything is enqueued.  Graph capture is allowed (no allocation, no host
- * synchronisation, no memset nodes). */
+ * anything is enqueued.  Graph capture is allowed (see "Graph capture"
+ * below). */
 int symba_kick_encounter(symba_ctx *ctx, const symba_state *s, int64_t n, int64_t n_m,
                          double dt, double rcrit_factor, const symba_out *out, void *stream);
 
-/* Many independent problems in one persistent launch (the paper's
+/* Many independent problems in one set of launches (the paper's
  * parameter-space scans run many simulations; Sec. 1).  Each problem's
  * outputs are those of symba_kick_encounter on it.  The total of the n's must
  * not exceed the context's max_n and the total pair storage is the context's
- * max_pairs, shared in problem order.  problems: host array of n_problems. */
+ * max_pairs, shared in problem order.  problems: host array of n_problems.
+ * Graph capture is allowed (see "Graph capture" below).
+ *
+ * Graph capture.  symba_kick_encounter, symba_kick_encounter_batch,
+ * symba_step and symba_step_batch may be captured into a HIP graph.  A
+ * captured call allocates nothing, synchronises nothing and records no memset
+ * node; the per-problem descriptors of a captured batch are copied into a
+ * capture arena of the context that is only ever appended to, so later calls
+ * on the context, captured or not, never change what a graph replays.  The
+ * context's partial-sum buffer is never freed while a captured call may use
+ * it.  Limits: (1) a captured call that needs a larger partial-sum buffer
+ * than the context holds returns SYMBA_EINVAL (run the same problem sizes
+ * once outside capture first); (2) the capture arena holds 8 MiB of
+ * descriptors (about 13,000 problems over all captured batches of the
+ * context's life); a capture beyond it returns SYMBA_ENOMEM; (3) graphs and
+ * calls on one context share its scratch, so their executions must not
+ * overlap (replay them on the stream the context serves, or order them);
+ * (4) symba_autotune, symba_read_timing and symba_read_stats synchronise and
+ * must not be captured, and SYMBA_OPT_TIMING records nothing under capture. */
 int symba_kick_encounter_batch(symba_ctx *ctx, const symba_problem *problems, int32_t n_problems,
                                void *stream);
 
@@ -219,8 +237,8 @@ int symba_step(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, do
 
 /* symba_step for many independent simulations in one set of launches, each
  * with its own h; every simulation's state and outputs are the same bits as
- * its own symba_step call would give.  Graph-capturable after a first call
- * of the same shape (the descriptors are staged in pinned memory). */
+ * its own symba_step call would give.  Graph capture is allowed (see "Graph
+ * capture" above). */
 int symba_step_batch(symba_ctx *ctx, const symba_step_problem *steps, int32_t n_problems, void *stream);
 
 /* Host-only helper (no device work): the task list of the folded trapezoid

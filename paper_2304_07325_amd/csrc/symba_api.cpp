@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/symba.h"
+#include "symba_arena.h"
 #include "symba_internal.h"
 
 using symba::Desc;
@@ -41,6 +42,12 @@ struct symba_ctx {
     int32_t *bin_temp = nullptr;             // [kBinTempInts]: cell counts and fills (zero between calls), starts
     double *partial = nullptr;
     size_t partial_bytes = 0;
+    bool partial_captured = false;          // a captured call references the current partial buffer
+    std::vector<double *> partial_retired;  // earlier partial buffers a captured call may use (freed at destroy)
+    // capture arena: descriptors of calls made under stream capture, append-only
+    char *cap_pinned = nullptr;
+    char *cap_dev = nullptr;
+    symba::BumpArena cap_arena;
     Desc *descs_dev = nullptr;   // [max_problems]
     Desc *descs_pinned = nullptr;
     std::vector<Desc> descs_last;  // what descs_dev currently holds
@@ -62,6 +69,7 @@ struct symba_ctx {
 namespace {
 
 constexpr int kMaxProblems = 4096;
+constexpr size_t kCaptureArenaBytes = size_t(8) << 20;  // descriptors of captured calls
 constexpr int kMaxSplit = 8;  // most split diagonals SYMBA_OPT_SPLIT accepts
 // Pair-scatter blocks (final kernel) and closing blocks per problem: a single
 // call spreads them wide, a batch of many problems less so.
@@ -228,20 +236,49 @@ bool bad_out(const symba_out *o) {
            !o->status || o->pair_cap < 0 || (o->pair_cap > 0 && (!o->pair_i || !o->pair_j));
 }
 
-int grow_partial(symba_ctx *c, size_t doubles) {
-    const size_t bytes = std::max<size_t>(doubles * sizeof(double), 256);
-    if (bytes <= c->partial_bytes) return SYMBA_OK;
-    if (c->partial) {
-        if (hipFree(c->partial) != hipSuccess) return SYMBA_EDEVICE;
-        c->partial = nullptr;
-        c->partial_bytes = 0;
+// True while `stream` is being captured into a graph (nothing may be
+// allocated, freed or synchronised then).
+bool is_capturing(hipStream_t stream) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// The partial-sum buffer for a call that needs `doubles` of it (see
+// symba::plan_partial): grown geometrically when too small; a buffer a
+// captured call has used is retired rather than freed; no growth under
+// capture (SYMBA_EINVAL: run the shape once outside capture first).
+int grow_partial(symba_ctx *c, size_t doubles, bool capturing) {
+    const size_t need = std::max<size_t>(doubles * sizeof(double), 256);
+    const symba::PartialAction a = symba::plan_partial(c->partial_bytes, need, c->partial_captured, capturing);
+    if (a.kind == symba::PartialAction::Refuse) return SYMBA_EINVAL;
+    if (a.kind == symba::PartialAction::Grow) {
+        double *fresh = nullptr;
+        if (hipMalloc(&fresh, a.new_bytes) != hipSuccess) return SYMBA_ENOMEM;
+        if (c->partial) {
+            if (a.retire_old)
+                c->partial_retired.push_back(c->partial);
+            else if (hipFree(c->partial) != hipSuccess)
+                return SYMBA_EDEVICE;
+        }
+        c->partial = fresh;
+        c->partial_bytes = a.new_bytes;
+        c->partial_captured = false;
     }
-    if (hipMalloc(&c->partial, bytes) != hipSuccess) {
-        c->partial = nullptr;
-        return SYMBA_ENOMEM;
-    }
-    c->partial_bytes = bytes;
+    if (capturing) c->partial_captured = true;
     return SYMBA_OK;
+}
+
+// Device copy of `bytes` of host data for a call made under capture: staged
+// in the capture arena (pinned and device halves at the same offset), copied
+// by a captured node that every replay repeats from the same, never
+// rewritten, pinned bytes.  Null when the arena is full.
+void *capture_upload(symba_ctx *c, const void *src, size_t bytes, hipStream_t stream) {
+    size_t off = 0;
+    if (!c->cap_arena.alloc(bytes, 256, off)) return nullptr;
+    std::memcpy(c->cap_pinned + off, src, bytes);
+    if (hipMemcpyAsync(c->cap_dev + off, c->cap_pinned + off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return nullptr;
+    return c->cap_dev + off;
 }
 
 void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int64_t n_m, double dt,
@@ -314,8 +351,11 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->bin_bbox, sizeof(unsigned long long) * 12) == hipSuccess &&
               hipMalloc(&c->bin_temp, sizeof(int32_t) * symba::kBinTempInts) == hipSuccess &&
               hipMalloc(&c->descs_dev, sizeof(Desc) * kMaxProblems) == hipSuccess &&
+              hipMalloc(&c->cap_dev, kCaptureArenaBytes) == hipSuccess &&
+              hipHostMalloc(&c->cap_pinned, kCaptureArenaBytes, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
+    c->cap_arena = symba::BumpArena(kCaptureArenaBytes);
     if (ok) {
         ok = hipMemset(c->parent, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->touched, 0, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -361,6 +401,9 @@ int symba_ctx_destroy(symba_ctx *c) {
     (void)hipFree(c->bin_bbox);
     (void)hipFree(c->bin_temp);
     (void)hipFree(c->partial);
+    for (double *p : c->partial_retired) (void)hipFree(p);
+    (void)hipFree(c->cap_dev);
+    if (c->cap_pinned) (void)hipHostFree(c->cap_pinned);
     (void)hipFree(c->descs_dev);
     if (c->descs_pinned) (void)hipHostFree(c->descs_pinned);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
@@ -417,7 +460,7 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
     const int rows = rows_for(c, n_tri_guess);
     const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
     const Plan p = make_plan(n, n_m, rows, field_rows, split_for(c, n_tri_guess, rows));
-    int rc = grow_partial(c, p.partial_doubles);
+    int rc = grow_partial(c, p.partial_doubles, is_capturing((hipStream_t)stream));
     if (rc != SYMBA_OK) return rc;
     Desc d;
     fill_desc(d, *s, *out, n, n_m, dt, rcrit_factor, p, field_rows);
@@ -535,7 +578,9 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
         plans[s] = make_plan(q.n, q.n_m, rows[order[s]], frows[order[s]], split_for(c, n_tri, rows[order[s]]));
         partial_total += plans[s].partial_doubles;
     }
-    int rc = grow_partial(c, partial_total);
+    hipStream_t st = (hipStream_t)stream;
+    const bool capturing = is_capturing(st);
+    int rc = grow_partial(c, partial_total, capturing);
     if (rc != SYMBA_OK) return rc;
     int64_t task_total = 0, fin_total = 0, body_off = 0, blk_off = 0, pair_off = 0, box_off = 0, ind_off = 0;
     int n_binned = 0;
@@ -587,13 +632,14 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
         groups.back().n_tasks += d.n_tasks;
     }
     cfg.ind_blocks = ind_off;
-    hipStream_t st = (hipStream_t)stream;
     if (steps) {  // the drift descriptors, in the caller's order, each problem a range of blocks
-        if (c->steps_pending && hipEventSynchronize(c->steps_done) != hipSuccess) return SYMBA_EDEVICE;
+        if (!capturing && c->steps_pending && hipEventSynchronize(c->steps_done) != hipSuccess)
+            return SYMBA_EDEVICE;
+        std::vector<symba::StepDesc> sds((size_t)n_problems);
         int64_t blk = 0;
         for (int32_t k = 0; k < n_problems; ++k) {
             const symba_step_problem &q = steps[k];
-            symba::StepDesc &sd = c->steps_pinned[k];
+            symba::StepDesc &sd = sds[k];
             sd = symba::StepDesc{};
             sd.x = q.state.x; sd.y = q.state.y; sd.z = q.state.z;
             sd.vx = q.state.vx; sd.vy = q.state.vy; sd.vz = q.state.vz; sd.m = q.state.m;
@@ -609,28 +655,40 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
             sd.nblk = symba::step_blocks(q.n);
             blk += sd.nblk;
         }
-        if (hipMemcpyAsync(c->steps_dev, c->steps_pinned, sizeof(symba::StepDesc) * n_problems,
-                           hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipEventRecord(c->steps_done, st) != hipSuccess)
-            return SYMBA_EDEVICE;
-        c->steps_pending = true;
-        if (symba::launch_drifts(c->steps_pinned[0], c->steps_dev, n_problems, blk, st) != hipSuccess)
-            return SYMBA_EDEVICE;
+        const size_t sbytes = sizeof(symba::StepDesc) * n_problems;
+        symba::StepDesc *steps_dev = c->steps_dev;
+        if (capturing) {  // descriptors of its own, which no later call rewrites
+            steps_dev = (symba::StepDesc *)capture_upload(c, sds.data(), sbytes, st);
+            if (!steps_dev) return SYMBA_ENOMEM;
+        } else {
+            std::memcpy(c->steps_pinned, sds.data(), sbytes);
+            if (hipMemcpyAsync(c->steps_dev, c->steps_pinned, sbytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipEventRecord(c->steps_done, st) != hipSuccess)
+                return SYMBA_EDEVICE;
+            c->steps_pending = true;
+        }
+        if (symba::launch_drifts(sds[0], steps_dev, n_problems, blk, st) != hipSuccess) return SYMBA_EDEVICE;
     }
-    const bool same = c->descs_last.size() == ds.size() &&
-                      std::memcmp(c->descs_last.data(), ds.data(), sizeof(Desc) * ds.size()) == 0;
-    if (!same) {
-        if (c->upload_pending && hipEventSynchronize(c->upload_done) != hipSuccess) return SYMBA_EDEVICE;
-        std::memcpy(c->descs_pinned, ds.data(), sizeof(Desc) * ds.size());
-        if (hipMemcpyAsync(c->descs_dev, c->descs_pinned, sizeof(Desc) * ds.size(), hipMemcpyHostToDevice,
-                           st) != hipSuccess)
-            return SYMBA_EDEVICE;
-        if (hipEventRecord(c->upload_done, st) != hipSuccess) return SYMBA_EDEVICE;
-        c->upload_pending = true;
-        c->descs_last = ds;
+    const Desc *descs_dev = c->descs_dev;
+    if (capturing) {  // descriptors of its own, which no later call rewrites
+        descs_dev = (const Desc *)capture_upload(c, ds.data(), sizeof(Desc) * ds.size(), st);
+        if (!descs_dev) return SYMBA_ENOMEM;
+    } else {
+        const bool same = c->descs_last.size() == ds.size() &&
+                          std::memcmp(c->descs_last.data(), ds.data(), sizeof(Desc) * ds.size()) == 0;
+        if (!same) {
+            if (c->upload_pending && hipEventSynchronize(c->upload_done) != hipSuccess) return SYMBA_EDEVICE;
+            std::memcpy(c->descs_pinned, ds.data(), sizeof(Desc) * ds.size());
+            if (hipMemcpyAsync(c->descs_dev, c->descs_pinned, sizeof(Desc) * ds.size(), hipMemcpyHostToDevice,
+                               st) != hipSuccess)
+                return SYMBA_EDEVICE;
+            if (hipEventRecord(c->upload_done, st) != hipSuccess) return SYMBA_EDEVICE;
+            c->upload_pending = true;
+            c->descs_last = ds;
+        }
     }
-    hipError_t e = symba::launch_step(ds.data(), c->descs_dev, n_problems, groups.data(), (int)groups.size(),
-                                      n_binned, fin_total, cfg, st, timing_slot(c));
+    hipError_t e = symba::launch_step(ds.data(), descs_dev, n_problems, groups.data(), (int)groups.size(),
+                                      n_binned, fin_total, cfg, st, capturing ? nullptr : timing_slot(c));
     return e == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
 }
 
