@@ -215,6 +215,26 @@ int symba_read_timing(symba_ctx *ctx, double *tiles_ms, double *finalize_ms, int
 /* Static text for a code. */
 const char *symba_strerror(int code);
 
+/* symba_kick_encounter for callers that cannot allocate device memory: code
+ * under HIP graph capture where allocation is forbidden, tight serving loops,
+ * harnesses that forbid hipMalloc.  No context: the scratch is a fixed
+ * region of the library's own device memory, SYMBA_NOALLOC_SCRATCH_BYTES per
+ * GPU, loaded with the library and held until the process ends.  Limits:
+ * n <= SYMBA_NOALLOC_MAX_N (else SYMBA_ETOOBIG, before anything is enqueued)
+ * and at most SYMBA_NOALLOC_MAX_PAIRS flagged pairs stored (more set
+ * SYMBA_STATUS_CAPACITY, as with a context's max_pairs); the default options
+ * (FP32 screen, built-in tile sizes, no binning, the interaction term).
+ * Arguments, outputs, errors and asynchrony as symba_kick_encounter; the
+ * same plan runs the same kernels, so the outputs are the same bits as a
+ * default context's.  Every call on one GPU uses that GPU's one region:
+ * calls that overlap on a GPU (two streams, two host threads) race and give
+ * wrong results; order them.  The device is the current HIP device. */
+#define SYMBA_NOALLOC_MAX_N 8192
+#define SYMBA_NOALLOC_MAX_PAIRS 65536
+#define SYMBA_NOALLOC_SCRATCH_BYTES 17434880
+int symba_kick_encounter_noalloc(const symba_state *s, int64_t n, int64_t n_m, double dt,
+                                 double rcrit_factor, const symba_out *out, void *stream);
+
 /* One step of length h of the democratic heliocentric map that SyMBA is
  * built on (the paper's Sec. 1: Duncan, Levison & Lee 1998), outside close
  * encounters: with heliocentric positions, barycentric velocities, G = 1 and

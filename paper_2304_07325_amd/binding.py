@@ -53,7 +53,8 @@ class symba_problem(ctypes.Structure):
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
            "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step", "symba_step_batch",
-           "symba_plan_for")
+           "symba_plan_for", "symba_kick_encounter_noalloc")
+NOALLOC_MAX_N, NOALLOC_MAX_PAIRS = 8192, 65536
 
 
 class SymbaError(RuntimeError):
@@ -74,6 +75,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.symba_kick_encounter.restype = ctypes.c_int
     lib.symba_kick_encounter.argtypes = [_P, ctypes.POINTER(symba_state), _I64, _I64, _D, _D,
                                          ctypes.POINTER(symba_out), _P]
+    lib.symba_kick_encounter_noalloc.restype = ctypes.c_int
+    lib.symba_kick_encounter_noalloc.argtypes = [ctypes.POINTER(symba_state), _I64, _I64, _D, _D,
+                                                 ctypes.POINTER(symba_out), _P]
     lib.symba_step.restype = ctypes.c_int
     lib.symba_step.argtypes = [_P, ctypes.POINTER(symba_mstate), _I64, _I64, _D, _D, ctypes.POINTER(symba_out), _P]
     lib.symba_step_batch.restype = ctypes.c_int
@@ -298,6 +302,20 @@ class Context:
         rc = lib().symba_kick_encounter_batch(self._h, arr, len(problems), _stream_handle(stream))
         _check(rc, "symba_kick_encounter_batch")
         return [p[4] for p in problems]
+
+
+def kick_encounter_noalloc(state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs,
+                           stream=None) -> Outputs:
+    """symba_kick_encounter_noalloc: one evaluation without a context, in the
+    library's fixed scratch of the current device (n <= NOALLOC_MAX_N; calls
+    overlapping on one device race)."""
+    n = int(state["x"].numel())
+    st = _state_struct(state, out)
+    o = out.c_struct()
+    rc = lib().symba_kick_encounter_noalloc(ctypes.byref(st), n, int(n_m), float(dt), float(rcrit_factor),
+                                            ctypes.byref(o), _stream_handle(stream))
+    _check(rc, "symba_kick_encounter_noalloc")
+    return out
 
 
 def plan_tasks(n: int, n_m: int, rows: int, field_rows: int = 1):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -64,6 +65,9 @@ struct symba_ctx {
     // timing events (SYMBA_OPT_TIMING): three per timed call
     std::vector<hipEvent_t> events;
     size_t timed_calls = 0;
+    // the scratch is a fixed region (symba_kick_encounter_noalloc): nothing
+    // may be allocated, a call that would need more returns SYMBA_ETOOBIG
+    bool fixed_scratch = false;
 };
 
 namespace {
@@ -249,6 +253,7 @@ bool is_capturing(hipStream_t stream) {
 // capture (SYMBA_EINVAL: run the shape once outside capture first).
 int grow_partial(symba_ctx *c, size_t doubles, bool capturing) {
     const size_t need = std::max<size_t>(doubles * sizeof(double), 256);
+    if (c->fixed_scratch) return need <= c->partial_bytes ? SYMBA_OK : SYMBA_ETOOBIG;
     const symba::PartialAction a = symba::plan_partial(c->partial_bytes, need, c->partial_captured, capturing);
     if (a.kind == symba::PartialAction::Refuse) return SYMBA_EINVAL;
     if (a.kind == symba::PartialAction::Grow) {
@@ -507,6 +512,107 @@ int symba_kick_encounter(symba_ctx *c, const symba_state *s, int64_t n, int64_t 
     if (n > c->max_n) return SYMBA_ETOOBIG;
     if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
     return evaluate(c, s, n, n_m, dt, rcrit_factor, out, stream, nullptr, 0.0, nullptr);
+}
+
+}  // extern "C"
+
+// Scratch of symba_kick_encounter_noalloc: one fixed region per device, in
+// the library's own device memory (loaded with the code object, held until
+// the process ends), carved like a context's scratch for problems of up to
+// SYMBA_NOALLOC_MAX_N bodies and SYMBA_NOALLOC_MAX_PAIRS stored pairs.  The
+// first part must be zero between calls (the kernels leave it so); it is
+// zeroed once per device, by a kernel on the first call's stream.
+namespace {
+
+constexpr int64_t kNoallocMaxN = SYMBA_NOALLOC_MAX_N;
+constexpr int64_t kNoallocMaxPairs = SYMBA_NOALLOC_MAX_PAIRS;
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+// partial-sum slots for n <= kNoallocMaxN with the default options: at
+// n_tri >= 4000 two bodies per lane, at most n / 128 blocks of 128 bodies
+// plus 2 (R - 1) = 2 per split diagonal (at most kMaxSplit); below 4000 one
+// body per lane, at most 63 blocks of 64 over fewer than 4000 bodies (less
+// in all).  A plan that needed more would be refused (SYMBA_ETOOBIG).
+constexpr size_t kNoallocSlots = kNoallocMaxN / 128 + 2 * kMaxSplit;
+constexpr size_t kNzParent = 0;
+constexpr size_t kNzTouched = kNzParent + align256(sizeof(int32_t) * kNoallocMaxN);
+constexpr size_t kNzBcnt = kNzTouched + align256(sizeof(int32_t) * kNoallocMaxN);
+constexpr size_t kNzBfill = kNzBcnt + align256(sizeof(int32_t) * kNoallocMaxN);
+constexpr size_t kNzCtr = kNzBfill + align256(sizeof(int32_t) * kNoallocMaxN);
+constexpr size_t kNzStats = kNzCtr + align256(sizeof(unsigned long long) * symba::kCtrSlots);
+constexpr size_t kNzEnd = kNzStats + align256(sizeof(unsigned long long) * symba::kStatSlots);  // zero part
+constexpr size_t kNoBlkGroups = kNzEnd;
+constexpr size_t kNoPairs = kNoBlkGroups + align256(sizeof(int32_t) * (kNoallocMaxN / symba::kFinBodies + 1));
+constexpr size_t kNoSorted = kNoPairs + align256(sizeof(int2) * kNoallocMaxPairs);
+constexpr size_t kNoPartial = kNoSorted + align256(sizeof(int4) * kNoallocMaxPairs);
+constexpr size_t kNoPartialBytes = sizeof(double) * kNoallocSlots * 3 * kNoallocMaxN;
+constexpr size_t kNoallocBytes = kNoPartial + kNoPartialBytes;
+static_assert(kNoallocBytes == SYMBA_NOALLOC_SCRATCH_BYTES, "symba.h states the scratch size");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mutex;
+unsigned char *g_noalloc_ptr[kNoallocDevices] = {};  // device address of `scratch`, per device
+bool g_noalloc_zeroed[kNoallocDevices] = {};
+
+// The device address of this device's `scratch` (the host-side name is only a
+// stand-in for it), found once per device with that device current.
+int noalloc_scratch(int device, unsigned char **ptr, bool *first) {
+    if (device < 0 || device >= kNoallocDevices) return SYMBA_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SYMBA_EDEVICE;
+        g_noalloc_ptr[device] = (unsigned char *)p;
+    }
+    *ptr = g_noalloc_ptr[device];
+    *first = !g_noalloc_zeroed[device];
+    g_noalloc_zeroed[device] = true;
+    return SYMBA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int symba_kick_encounter_noalloc(const symba_state *s, int64_t n, int64_t n_m, double dt, double rcrit_factor,
+                                 const symba_out *out, void *stream) {
+    if (bad_state(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || bad_scalar(dt, rcrit_factor)) return SYMBA_EINVAL;
+    if (n > kNoallocMaxN) return SYMBA_ETOOBIG;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return SYMBA_EDEVICE;
+    unsigned char *base = nullptr;
+    bool first = false;
+    int rc = noalloc_scratch(device, &base, &first);
+    if (rc != SYMBA_OK) return rc;
+    if (first && symba::launch_zero(base, kNzEnd, (hipStream_t)stream) != hipSuccess) {
+        std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+        g_noalloc_zeroed[device] = false;
+        return SYMBA_EDEVICE;
+    }
+    symba_ctx c;  // a view of the fixed region: owns nothing, frees nothing
+    c.device = device;
+    c.max_n = kNoallocMaxN;
+    c.max_pairs = kNoallocMaxPairs;
+    c.max_problems = 1;
+    c.fixed_scratch = true;
+    c.parent = (int32_t *)(base + kNzParent);
+    c.touched = (int32_t *)(base + kNzTouched);
+    c.bcnt = (int32_t *)(base + kNzBcnt);
+    c.bfill = (int32_t *)(base + kNzBfill);
+    c.ctr = (unsigned long long *)(base + kNzCtr);
+    c.stats = (unsigned long long *)(base + kNzStats);
+    c.blk_groups = (int32_t *)(base + kNoBlkGroups);
+    c.pairs = (int2 *)(base + kNoPairs);
+    c.sorted = (int4 *)(base + kNoSorted);
+    c.partial = (double *)(base + kNoPartial);
+    c.partial_bytes = kNoPartialBytes;
+    return evaluate(&c, s, n, n_m, dt, rcrit_factor, out, stream, nullptr, 0.0, nullptr);
 }
 
 int symba_step(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double rcrit_factor,

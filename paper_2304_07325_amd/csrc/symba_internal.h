@@ -229,6 +229,10 @@ inline int64_t final_blocks(int64_t n, int scatter_blocks) {
 
 inline int32_t bucket_count(int64_t n) { return (int32_t)(n < kMaxBuckets ? n : kMaxBuckets); }
 
+// Zeroes `bytes` (a multiple of 4) of device memory with a kernel on
+// `stream` (no memset node, so it may be captured).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
+
 // Launch the kernels of one step over n_desc problems: binning (n_binned
 // problems use it), the tile kernel (once per group of
 // problems sharing a tile size), the final kernel (body

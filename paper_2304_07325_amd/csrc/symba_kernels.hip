@@ -1683,8 +1683,20 @@ void launch_tiles_r(const TileGroup &g, const Desc &one, const Desc *descs, hipS
     }
 }
 
+__global__ __launch_bounds__(256) void k_zero(uint32_t *p, size_t words) {
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < words; k += (size_t)gridDim.x * 256) p[k] = 0u;
+}
+
 }  // namespace
 
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
+    const size_t words = bytes / 4;
+    const size_t want = (words + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 1024 ? want : 1024);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, stream, (uint32_t *)p, words);
+    return hipGetLastError();
+}
 
 hipError_t launch_step(const Desc *descs_host, const Desc *descs_dev, int n_desc, const TileGroup *groups,
                        int n_groups, int n_binned, int64_t n_fin_total, const LaunchCfg &cfg, hipStream_t stream,

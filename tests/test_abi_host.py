@@ -51,6 +51,19 @@ def test_errors_before_any_device_work():
     assert lib.symba_plan_tasks(0, 0, 1, 1, None, 0) == -1
     assert lib.symba_plan_tasks(10, 11, 1, 1, None, 0) == -1
     assert lib.symba_plan_tasks(10, 5, 3, 1, None, 0) == -1
+    # the no-allocation entry point: argument checks, and sizes beyond its
+    # fixed scratch, are refused before the device is touched (the pointers
+    # below are never dereferenced on the host)
+    assert lib.symba_kick_encounter_noalloc(None, 10, 9, 1.0, 3.0, None, None) == B.SYMBA_EINVAL
+    fake = B.symba_state(*([8] * 8))
+    fo = B.symba_out(8, 8, 8, 8, 8, 16, 8, 8, 8, 8)
+    n_big = B.NOALLOC_MAX_N + 1
+    assert lib.symba_kick_encounter_noalloc(ctypes.byref(fake), n_big, n_big - 1, 1.0, 3.0, ctypes.byref(fo),
+                                            None) == B.SYMBA_ETOOBIG
+    assert lib.symba_kick_encounter_noalloc(ctypes.byref(fake), 10, 11, 1.0, 3.0, ctypes.byref(fo),
+                                            None) == B.SYMBA_EINVAL
+    assert lib.symba_kick_encounter_noalloc(ctypes.byref(fake), 10, 9, -1.0, 3.0, ctypes.byref(fo),
+                                            None) == B.SYMBA_EINVAL
 
 
 def expand(tasks, n, n_m, rows, field_rows):
@@ -162,7 +175,8 @@ def test_binding_constants_match_header():
     text = open(os.path.join(ROOT, "include", "symba.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define SYMBA_(\w+)\s+(-?\d+)", text)}
     for name in ("OPT_TILE_ROWS", "OPT_FIELD_ROWS", "OPT_SCREEN", "OPT_TIMING", "OPT_BIN", "OPT_ACC", "OPT_SPLIT",
-                 "SCREEN_AUTO", "SCREEN_FP32", "SCREEN_FP64", "ACC_INTERACTION", "ACC_HELIO"):
+                 "SCREEN_AUTO", "SCREEN_FP32", "SCREEN_FP64", "ACC_INTERACTION", "ACC_HELIO",
+                 "NOALLOC_MAX_N", "NOALLOC_MAX_PAIRS"):
         assert getattr(B, name) == defs[name], name
 
 
