@@ -176,6 +176,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-lanes", type=int, default=2, help="serving calls in flight at once")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -478,33 +479,78 @@ def bench_other_workloads(args, B, dg, torch):
     return res
 
 
+class _ServeWatchdog:
+    """Ends the process with a non-zero status (and a line naming the run)
+    when a serving loop has neither issued nor completed a call for
+    `limit_s` seconds: a stalled run stops at once instead of going silent."""
+
+    def __init__(self, srv, limit_s: float, what: str):
+        import threading
+        self.srv, self.limit_s, self.what = srv, limit_s, what
+        self.served = 0
+        self.stop = threading.Event()
+        self.thread = threading.Thread(target=self._run, daemon=True)
+
+    def progress(self, served, n_req):
+        step = max(n_req // 4, 1)
+        if served // step > self.served // step:
+            log(f"  {self.what}: {served}/{n_req} requests served")
+        self.served = served
+
+    def _run(self):
+        while not self.stop.wait(0.5):
+            idle = time.monotonic() - self.srv.last_progress
+            if idle > self.limit_s:
+                print(f"serving watchdog: {self.what} made no progress for {idle:.1f} s "
+                      f"({self.served} requests served, {len(self.srv.busy)} simulations in running calls)",
+                      file=sys.stderr, flush=True)
+                os._exit(3)
+
+    def __enter__(self):
+        self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        self.thread.join()
+
+
 def bench_serve(args, dg, torch):
     """256 resident simulations (N log-uniform in [500, 50000], all massive,
     even ids cold and odd ids hot), step requests arriving as a Poisson stream
-    that names a uniformly random simulation, served by continuous batching:
-    latency from arrival to completion (host monotonic clock).  Run with a
-    200 GB device budget (nothing is evicted) and again with 0.5 GB, which
-    keeps only part of the population resident.  Then at saturation (every
-    request waiting from the start): served steps/s against the same requests
-    as plain per-simulation calls."""
+    that names a uniformly random simulation, served by continuous batching
+    with `--serve-lanes` calls in flight: latency from arrival to completion
+    (host monotonic clock).  Run with a 200 GB device budget (nothing is
+    evicted), again with one call in flight, and with 0.5 GB, which keeps only
+    part of the population resident.  Then at saturation (every request
+    waiting from the start): served steps/s with one and with several calls
+    in flight against the same requests as plain per-simulation calls.  Each
+    serving loop runs under a watchdog that ends the process at its first
+    stall."""
     from paper_2304_07325_amd.serve import Server
     dt, f = dg.DT_HALF_YEAR, dg.RCRIT_FACTOR
+    lanes = args.serve_lanes
     pop = dg.serving_population()
     sims = [(dg.make_disk(n, nm, kind, seed).state(0), nm) for (n, nm, kind, seed) in pop]
     total = sum(n for n, _, _, _ in pop)
-    res = {"simulations": len(sims), "bodies": total, "rate_hz": args.serve_rate}
-    runs = (("budget_200GB", 200 << 30, None, args.serve_requests, args.serve_warmup),
-            ("budget_0.5GB", 512 << 20, 100_000, args.serve_requests // 5, args.serve_warmup // 5))
-    for name, budget, max_bodies, n_req, warm in runs:
+    res = {"simulations": len(sims), "bodies": total, "rate_hz": args.serve_rate, "lanes": lanes}
+    runs = (("budget_200GB", 200 << 30, None, args.serve_requests, args.serve_warmup, lanes),
+            ("budget_200GB_one_call_in_flight", 200 << 30, None, args.serve_requests // 4,
+             args.serve_warmup // 4, 1),
+            ("budget_0.5GB", 512 << 20, 100_000, args.serve_requests // 5, args.serve_warmup // 5, lanes))
+    for name, budget, max_bodies, n_req, warm, n_lanes in runs:
         t, ids = dg.poisson_arrivals(args.serve_rate, n_req + warm, len(sims))
-        srv = Server(sims, budget, dt, f, max_batch_bodies=max_bodies)
-        srv.preload(reserve=max(srv._need(k) - srv.sims[k].resident_bytes for k in range(len(sims))))
+        srv = Server(sims, budget, dt, f, max_batch_bodies=max_bodies, lanes=n_lanes)
+        srv.preload(reserve=n_lanes * max(srv._need(k) - srv.sims[k].resident_bytes for k in range(len(sims))))
         torch.cuda.synchronize()
-        stats = srv.serve(t, ids, warmup=warm)
+        log(f"serve {name}: {n_req + warm} requests at {args.serve_rate:.0f}/s, {n_lanes} lane(s)")
+        with _ServeWatchdog(srv, 20.0, f"serve {name}") as wd:
+            stats = srv.serve(t, ids, warmup=warm, progress=wd.progress)
         srv.close()
         res[name] = stats
         log(f"serve {name}: p50 {stats['latency_ms']['p50']:.3f} ms p99 {stats['latency_ms']['p99']:.3f} ms, "
             f"{stats['steps_per_s']:.0f} steps/s, mean batch {stats['mean_batch']:.1f}, "
+            f"calls issued while another ran {stats['calls_issued_while_another_ran']}/{stats['calls']}, "
             f"uploads {stats['uploads']}, evictions {stats['evictions']}")
     # saturation: every request already waiting at t = 0, served by continuous
     # batching, against the same requests in the same order as plain
@@ -512,26 +558,34 @@ def bench_serve(args, dg, torch):
     import numpy as np
     n_sat = max(args.serve_requests // 10, 1)
     _, ids = dg.poisson_arrivals(args.serve_rate, n_sat, len(sims))
-    srv = Server(sims, 200 << 30, dt, f)
-    srv.preload()
-    torch.cuda.synchronize()
-    stats = srv.serve(np.zeros(n_sat), ids)
-    for k in ids[:20]:   # warm the plain path
-        srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in ids:
-        srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    pairs = stats["pairs_per_s"] * n_sat / stats["steps_per_s"]
-    srv.close()
-    res["saturated"] = {"requests": n_sat, "served_steps_per_s": stats["steps_per_s"],
-                        "served_pairs_per_s": stats["pairs_per_s"], "mean_batch": stats["mean_batch"],
-                        "calls": stats["calls"], "plain_steps_per_s": n_sat / plain_s,
-                        "plain_pairs_per_s": pairs / plain_s}
-    log(f"serve saturated: {stats['steps_per_s']:.0f} steps/s served (mean batch {stats['mean_batch']:.1f}) "
-        f"vs {n_sat / plain_s:.0f} steps/s as plain calls")
+    sat = {"requests": n_sat}
+    for n_lanes in sorted({1, lanes}):
+        srv = Server(sims, 200 << 30, dt, f, lanes=n_lanes)
+        srv.preload()
+        torch.cuda.synchronize()
+        with _ServeWatchdog(srv, 20.0, f"serve saturated, {n_lanes} lane(s)") as wd:
+            stats = srv.serve(np.zeros(n_sat), ids, progress=wd.progress)
+        sat[f"lanes_{n_lanes}"] = {"served_steps_per_s": stats["steps_per_s"],
+                                   "served_pairs_per_s": stats["pairs_per_s"], "mean_batch": stats["mean_batch"],
+                                   "calls": stats["calls"],
+                                   "calls_issued_while_another_ran": stats["calls_issued_while_another_ran"]}
+        log(f"serve saturated, {n_lanes} lane(s): {stats['steps_per_s']:.0f} steps/s "
+            f"(mean batch {stats['mean_batch']:.1f}, {stats['calls']} calls)")
+        if n_lanes == lanes:
+            for k in ids[:20]:   # warm the plain path
+                srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in ids:
+                srv.ctx.kick_encounter(srv.sims[k].dev, srv.sims[k].n_m, dt, f, out=srv.sims[k].out)
+            torch.cuda.synchronize()
+            plain_s = time.perf_counter() - t0
+            pairs = stats["pairs_per_s"] * n_sat / stats["steps_per_s"]
+            sat.update(plain_steps_per_s=n_sat / plain_s, plain_pairs_per_s=pairs / plain_s)
+        srv.close()
+    res["saturated"] = sat
+    log(f"serve saturated: {sat[f'lanes_{lanes}']['served_steps_per_s']:.0f} steps/s served with {lanes} lane(s) "
+        f"vs {sat['plain_steps_per_s']:.0f} steps/s as plain calls")
     return res
 
 

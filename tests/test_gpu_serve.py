@@ -162,3 +162,39 @@ def test_run_batch_on_a_side_stream():
         for key in ("x", "y", "z", "vx", "vy", "vz"):
             assert got[key].tobytes() == want[k][key].tobytes(), (k, key)
     server.close()
+
+
+def test_overlapped_calls_match_single_calls():
+    """Two calls in flight: a large simulation's call is running when
+    requests for small ones arrive, so they go out on the second lane at
+    once; a second request for the large simulation waits for its first call.
+    Every output is the same bits as a single call on that simulation alone."""
+    from paper_2304_07325_amd.serve import Server
+    specs = [(30000, 29999, "cold", 90), (500, 499, "hot", 91), (800, 80, "cold", 92), (1200, 1199, "hot", 93),
+             (300, 299, "cold", 94)]
+    sims = [(dg.make_disk(n, nm, kind, seed).state(0), nm) for (n, nm, kind, seed) in specs]
+    ref = _alone(sims)
+    ids = [0, 1, 2, 3, 0, 4, 1, 0, 2, 3]
+    t = [0.0, 1e-4, 2e-4, 3e-4, 4e-4, 5e-4, 6e-4, 7e-4, 8e-4, 9e-4]
+    G.say("overlapped serving, requests", len(ids))
+    server = Server(sims, 1 << 34, DT, F, lanes=2)
+    server.preload()
+    import torch
+    torch.cuda.synchronize()
+    seen = []
+
+    def check(r, k, out):
+        got = out.to_host()
+        want = ref[k]
+        assert got["acc"].tobytes() == want["acc"].tobytes(), f"request {r} (sim {k}): acc differs"
+        assert np.array_equal(got["pair_i"], want["pair_i"]) and np.array_equal(got["pair_j"], want["pair_j"])
+        assert np.array_equal(got["group_id"], want["group_id"]) and got["n_groups"] == want["n_groups"]
+        seen.append(r)
+
+    stats = server.serve(t, ids, on_complete=check)
+    print(stats)
+    assert sorted(seen) == list(range(len(ids)))
+    assert stats["calls_issued_while_another_ran"] >= 1
+    big = [r for r in seen if ids[r] == 0]
+    assert big == sorted(big)
+    server.close()
