@@ -58,6 +58,11 @@ extern "C" {
 /* Bits of the device-side status word (symba_out.status). */
 #define SYMBA_STATUS_CAPACITY 1   /* more flagged pairs than fit; *n_pairs holds the true count */
 #define SYMBA_STATUS_NONFINITE 2  /* an acceleration is Inf or NaN (e.g. coincident bodies) */
+#define SYMBA_STATUS_ENC_SKIPPED 4  /* symba_step_enc / symba_enc_prepare: some flagged pairs were not
+                                       resolved through the shells (more than SYMBA_ENC_MAX_PAIRS flagged
+                                       pairs, a group of more than SYMBA_ENC_MAX_GROUP_PAIRS pairs, or a
+                                       pair list that did not fit pair_cap): their bodies took the plain
+                                       step's Kepler drift and unweighted forces */
 
 /* Context options (symba_set_option). */
 #define SYMBA_OPT_TILE_ROWS 1   /* bodies per lane in triangle tiles: 1, 2 or 4 (0 = automatic) */
@@ -254,6 +259,46 @@ int symba_kick_encounter_noalloc(const symba_state *s, int64_t n, int64_t n_m, d
  * reversible).  Errors and asynchrony as symba_kick_encounter. */
 int symba_step(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, double h,
                double rcrit_factor, const symba_out *out, void *stream);
+
+/* The encounter step: symba_step with the close encounters resolved (the
+ * paper's Sec. 2, last paragraph: the encounter groups integrated in
+ * parallel, the pairs of a group one after the other; Sec. 3: SyMBA's
+ * M = 4 substeps per level, shell radius ratio 2.08, partition function f_l
+ * with l = 3, read as the degree-7 polynomial 35x^4 - 84x^5 + 70x^6 - 20x^7).
+ * A pair's shells have radii R_0 = rcrit_factor (rh_i + rh_j) and R_k =
+ * R_{k-1} / 2.08 (k <= 8); the pair potential is split over the levels by
+ * the partition function and every kick applies the exact gradient of its
+ * level's part.  The step is
+ *   v += (h/2) a0;  x += (h/2) P;  bodies in no flagged pair: Kepler drift
+ *   for h; each encounter group: 4 substeps of level 1, where a level-k
+ *   substep of length t kicks with the level's forces for t/2, tests its
+ *   pairs with radius R_k over t, drifts the bodies of unflagged pairs for t,
+ *   takes 4 substeps of level k + 1 for the flagged ones and kicks again;
+ *   x += (h/2) P;  evaluation at the new positions (symba_kick_encounter with
+ *   dt = |h|);  a0 reweighted to level 0;  v += (h/2) a0,
+ * where a0, the level-0 acceleration, weights each pair inside R_0 by the
+ * partition function.  The flagged pairs and groups of a step are those on
+ * entry in out (written by the previous step or by symba_enc_prepare).
+ * One workgroup integrates each group; a step takes at most
+ * SYMBA_ENC_MAX_PAIRS flagged pairs and SYMBA_ENC_MAX_GROUP_PAIRS pairs per
+ * group (beyond these SYMBA_STATUS_ENC_SKIPPED is set and those bodies take
+ * the plain step).  Mergers are not modelled.
+ * s: positions and velocities, updated in place.  out on entry: the level-0
+ * accelerations, pairs (lexicographic), groups and status of the current
+ * state; on return the same for the new state.  h may be negative.  Errors
+ * and asynchrony as symba_step; the step makes no host synchronisation, so
+ * it may be captured into a graph. */
+#define SYMBA_ENC_MAX_PAIRS 8192
+#define SYMBA_ENC_MAX_GROUP_PAIRS 255
+int symba_step_enc(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, double h,
+                   double rcrit_factor, const symba_out *out, void *stream);
+
+/* What symba_step_enc expects in out for state s: the evaluation of
+ * symba_kick_encounter (dt = |h|) with the accelerations of flagged pairs
+ * inside R_0 reweighted to level 0.  s is not changed.  Errors as
+ * symba_step_enc. */
+int symba_enc_prepare(symba_ctx *ctx, const symba_mstate *s, int64_t n, int64_t n_m, double h,
+                      double rcrit_factor, const symba_out *out, void *stream);
 
 /* symba_step for many independent simulations in one set of launches, each
  * with its own h; every simulation's state and outputs are the same bits as

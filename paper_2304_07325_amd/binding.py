@@ -16,7 +16,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsymba.so")
 
 SYMBA_OK, SYMBA_EINVAL, SYMBA_ENOMEM, SYMBA_EDEVICE, SYMBA_ETOOBIG = 0, 1, 2, 3, 4
-STATUS_CAPACITY, STATUS_NONFINITE = 1, 2
+STATUS_CAPACITY, STATUS_NONFINITE, STATUS_ENC_SKIPPED = 1, 2, 4
+ENC_MAX_PAIRS, ENC_MAX_GROUP_PAIRS = 8192, 255
 OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN, OPT_ACC, OPT_SPLIT = 1, 2, 4, 5, 6, 7, 8
 SCREEN_AUTO, SCREEN_FP32, SCREEN_FP64 = 0, 1, 2
 ACC_INTERACTION, ACC_HELIO = 0, 1
@@ -53,6 +54,7 @@ class symba_problem(ctypes.Structure):
 EXPORTS = ("symba_ctx_create", "symba_ctx_destroy", "symba_set_option", "symba_kick_encounter",
            "symba_kick_encounter_batch", "symba_strerror", "symba_plan_tasks", "symba_read_timing",
            "symba_scratch_bytes", "symba_autotune", "symba_read_stats", "symba_step", "symba_step_batch",
+           "symba_step_enc", "symba_enc_prepare",
            "symba_plan_for", "symba_kick_encounter_noalloc")
 NOALLOC_MAX_N, NOALLOC_MAX_PAIRS = 8192, 65536
 
@@ -80,6 +82,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                  ctypes.POINTER(symba_out), _P]
     lib.symba_step.restype = ctypes.c_int
     lib.symba_step.argtypes = [_P, ctypes.POINTER(symba_mstate), _I64, _I64, _D, _D, ctypes.POINTER(symba_out), _P]
+    for name in ("symba_step_enc", "symba_enc_prepare"):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = [_P, ctypes.POINTER(symba_mstate), _I64, _I64, _D, _D,
+                                       ctypes.POINTER(symba_out), _P]
     lib.symba_step_batch.restype = ctypes.c_int
     lib.symba_step_batch.argtypes = [_P, ctypes.POINTER(symba_step_problem), ctypes.c_int32, _P]
     lib.symba_kick_encounter_batch.restype = ctypes.c_int
@@ -259,6 +265,30 @@ class Context:
                               ctypes.byref(o), _stream_handle(stream))
         _check(rc, "symba_step")
         return out
+
+    def _enc_call(self, name, state, n_m, h, rcrit_factor, out, stream):
+        n = int(state["x"].numel())
+        _state_struct(state, out)
+        st = symba_mstate(*(state[k].data_ptr() for k in STATE_KEYS))
+        o = out.c_struct()
+        rc = getattr(lib(), name)(self._h, ctypes.byref(st), n, int(n_m), float(h), float(rcrit_factor),
+                                  ctypes.byref(o), _stream_handle(stream))
+        _check(rc, name)
+        return out
+
+    def enc_prepare(self, state: dict, n_m: int, h: float, rcrit_factor: float, out: Outputs,
+                    stream=None) -> Outputs:
+        """symba_enc_prepare: out := the evaluation at state with the flagged
+        pairs inside the critical radius reweighted to level 0 (the input of
+        step_enc)."""
+        return self._enc_call("symba_enc_prepare", state, n_m, h, rcrit_factor, out, stream)
+
+    def step_enc(self, state: dict, n_m: int, h: float, rcrit_factor: float, out: Outputs,
+                 stream=None) -> Outputs:
+        """symba_step_enc: one step with the encounter groups integrated through
+        the shells, in place on the device state; out holds the level-0
+        evaluation of the current state on entry and of the new one on return."""
+        return self._enc_call("symba_step_enc", state, n_m, h, rcrit_factor, out, stream)
 
     def step_batch(self, problems, stream=None):
         """symba_step_batch: problems = list of (device state, n_m, h, rcrit_factor, Outputs)."""

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsymba.so")
 SOURCES = [os.path.join(CSRC, "symba_kernels.hip"), os.path.join(CSRC, "symba_step.hip"),
-           os.path.join(CSRC, "symba_api.cpp")]
+           os.path.join(CSRC, "symba_enc.hip"), os.path.join(CSRC, "symba_api.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

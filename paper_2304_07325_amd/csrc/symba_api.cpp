@@ -65,6 +65,12 @@ struct symba_ctx {
     // timing events (SYMBA_OPT_TIMING): three per timed call
     std::vector<hipEvent_t> events;
     size_t timed_calls = 0;
+    // encounter step (symba_step_enc): group table and flags
+    int32_t *enc_gp = nullptr;      // [kEncMaxPairs]
+    int32_t *enc_gstart = nullptr;  // [kEncMaxPairs + 1]
+    int32_t *enc_gskip = nullptr;   // [kEncMaxPairs]
+    int32_t *enc_ctl = nullptr;     // [kEncCtlInts], zero between calls
+    int32_t *ingroup = nullptr;     // [max_n], zero between calls
     // the scratch is a fixed region (symba_kick_encounter_noalloc): nothing
     // may be allocated, a call that would need more returns SYMBA_ETOOBIG
     bool fixed_scratch = false;
@@ -359,7 +365,12 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
               hipMalloc(&c->cap_dev, kCaptureArenaBytes) == hipSuccess &&
               hipHostMalloc(&c->cap_pinned, kCaptureArenaBytes, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&c->descs_pinned, sizeof(Desc) * kMaxProblems, hipHostMallocDefault) == hipSuccess &&
-              hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(&c->enc_gp, sizeof(int32_t) * symba::kEncMaxPairs) == hipSuccess &&
+              hipMalloc(&c->enc_gstart, sizeof(int32_t) * (symba::kEncMaxPairs + 1)) == hipSuccess &&
+              hipMalloc(&c->enc_gskip, sizeof(int32_t) * symba::kEncMaxPairs) == hipSuccess &&
+              hipMalloc(&c->enc_ctl, sizeof(int32_t) * symba::kEncCtlInts) == hipSuccess &&
+              hipMalloc(&c->ingroup, sizeof(int32_t) * max_n) == hipSuccess;
     c->cap_arena = symba::BumpArena(kCaptureArenaBytes);
     if (ok) {
         ok = hipMemset(c->parent, 0, sizeof(int32_t) * max_n) == hipSuccess &&
@@ -370,6 +381,8 @@ int symba_ctx_create(symba_ctx **out, int device, int64_t max_n, int64_t max_pai
              hipMemset(c->bfill, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipMemset(c->ctr, 0, sizeof(unsigned long long) * symba::kCtrSlots * kMaxProblems) == hipSuccess &&
              hipMemset(c->stats, 0, sizeof(unsigned long long) * symba::kStatSlots) == hipSuccess &&
+             hipMemset(c->enc_ctl, 0, sizeof(int32_t) * symba::kEncCtlInts) == hipSuccess &&
+             hipMemset(c->ingroup, 0, sizeof(int32_t) * max_n) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {
@@ -413,6 +426,11 @@ int symba_ctx_destroy(symba_ctx *c) {
     if (c->descs_pinned) (void)hipHostFree(c->descs_pinned);
     if (c->upload_done) (void)hipEventDestroy(c->upload_done);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    (void)hipFree(c->enc_gp);
+    (void)hipFree(c->enc_gstart);
+    (void)hipFree(c->enc_gskip);
+    (void)hipFree(c->enc_ctl);
+    (void)hipFree(c->ingroup);
     delete c;
     return SYMBA_OK;
 }
@@ -460,7 +478,7 @@ namespace {
 // null, is the step's velocity arrays for the closing half kick of kick_h.
 int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double dt, double rcrit_factor,
              const symba_out *out, void *stream, double *const *kick, double kick_h,
-             const symba::StepDesc *drifts) {
+             const symba::StepDesc *drifts, bool interaction_only = false) {
     const int n_tri_guess = (int)(n_m >= n - 1 ? n : n_m);
     const int rows = rows_for(c, n_tri_guess);
     const int field_rows = field_rows_for(n - n_tri_guess, c->opt_field_rows);
@@ -489,7 +507,7 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
         d.kvy = kick[1];
         d.kvz = kick[2];
         d.kick_h = kick_h;
-    } else if (c->opt_acc == SYMBA_ACC_HELIO) {
+    } else if (c->opt_acc == SYMBA_ACC_HELIO && !interaction_only) {
         d.ind = c->ind;
         d.n_ind = ceil_div(d.n_tri, symba::kIndBodies);
         cfg.ind_blocks = d.n_ind;
@@ -638,6 +656,88 @@ int symba_step(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, doub
     const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
     double *const kick[3] = {s->vx, s->vy, s->vz};
     return evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, kick, 0.5 * h, &sd);
+}
+
+namespace {
+
+// The encounter step's view of a state, its outputs and the context's table.
+symba::EncDesc enc_desc(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double f,
+                        const symba_out *out) {
+    symba::EncDesc e{};
+    e.x = s->x; e.y = s->y; e.z = s->z; e.vx = s->vx; e.vy = s->vy; e.vz = s->vz; e.m = s->m; e.rh = s->rh;
+    e.ax = out->ax; e.ay = out->ay; e.az = out->az;
+    e.n = n;
+    e.n_tri = n_m >= n - 1 ? n : n_m;
+    e.f = f;
+    e.h = h;
+    e.kick_h = 0.5 * h;
+    e.pair_i = out->pair_i; e.pair_j = out->pair_j; e.n_pairs = out->n_pairs; e.status = out->status;
+    e.group_id = out->group_id;
+    e.pair_cap = out->pair_cap;
+    e.gp = c->enc_gp; e.gstart = c->enc_gstart; e.gskip = c->enc_gskip; e.ctl = c->enc_ctl;
+    e.ingroup = c->ingroup;
+    return e;
+}
+
+bool bad_mstate(const symba_mstate *s) {
+    return !s || !s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m || !s->rh;
+}
+
+// Level-0 reweighting of the evaluation in `out` (pairs, groups and
+// Newtonian accelerations at s), then the closing kick when e.kick_h != 0.
+int enc_finish(symba::EncDesc e, hipStream_t stream) {
+    e.mark = 0;
+    if (symba::launch_enc_table(e, stream) != hipSuccess || symba::launch_enc_level0(e, stream) != hipSuccess ||
+        symba::launch_enc_kick(e, stream) != hipSuccess)
+        return SYMBA_EDEVICE;
+    return SYMBA_OK;
+}
+
+}  // namespace
+
+int symba_enc_prepare(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double rcrit_factor,
+                      const symba_out *out, void *stream) {
+    if (!c || bad_mstate(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || !std::isfinite(h) || bad_scalar(std::fabs(h), rcrit_factor))
+        return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
+    int rc = evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, nullptr, 0.0, nullptr, true);
+    if (rc != SYMBA_OK) return rc;
+    symba::EncDesc e = enc_desc(c, s, n, n_m, h, rcrit_factor, out);
+    e.kick_h = 0.0;
+    return enc_finish(e, (hipStream_t)stream);
+}
+
+int symba_step_enc(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double rcrit_factor,
+                   const symba_out *out, void *stream) {
+    if (!c || bad_mstate(s) || bad_out(out)) return SYMBA_EINVAL;
+    if (n < 1 || n_m < 0 || n_m > n || !std::isfinite(h) || bad_scalar(std::fabs(h), rcrit_factor))
+        return SYMBA_EINVAL;
+    if (n > c->max_n) return SYMBA_ETOOBIG;
+    if (hipSetDevice(c->device) != hipSuccess) return SYMBA_EDEVICE;
+    symba::StepDesc sd{};
+    sd.x = s->x; sd.y = s->y; sd.z = s->z; sd.vx = s->vx; sd.vy = s->vy; sd.vz = s->vz; sd.m = s->m;
+    sd.ax = out->ax; sd.ay = out->ay; sd.az = out->az;
+    sd.n = n;
+    sd.n_tri = n_m >= n - 1 ? n : n_m;
+    sd.kick_h = 0.5 * h;
+    sd.sun_h = 0.5 * h;
+    sd.kepler_h = h;
+    sd.mom0 = c->mom;
+    sd.mom1 = c->mom + 3 * c->mom_blocks;
+    sd.blk_base = 0;
+    sd.nblk = symba::step_blocks(n);
+    sd.skip = c->ingroup;
+    symba::EncDesc e = enc_desc(c, s, n, n_m, h, rcrit_factor, out);
+    e.mark = 1;
+    const hipStream_t st = (hipStream_t)stream;
+    if (symba::launch_drifts_enc(sd, e, st) != hipSuccess) return SYMBA_EDEVICE;
+    const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
+    int rc = evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, nullptr, 0.0, nullptr, true);
+    if (rc != SYMBA_OK) return rc;
+    return enc_finish(e, st);
 }
 
 namespace {

@@ -1,0 +1,516 @@
+// Encounter groups through SyMBA's shells (the paper's Sec. 2, last
+// paragraph, and Sec. 3: M = 4 substeps per level, shell radius ratio 2.08,
+// the partition function f_l with l = 3).  The groups are integrated in
+// parallel, one workgroup each; inside a group the work is sequential in the
+// levels, parallel over bodies and pairs.
+//
+// Shells: a pair's critical radius R_0 = f (rh_i + rh_j) and R_k = R_{k-1} /
+// 2.08.  Partition: f_3(x) = 35 x^4 - 84 x^5 + 70 x^6 - 20 x^7 (from 0 to 1
+// with three vanishing derivatives at both ends); F_k(r) = f_3((r - R_{k+1}) /
+// (R_k - R_{k+1})) clipped to [0, 1], F_{-1} = 0.  Level weights W_k = F_k -
+// F_{k-1} (W_L = 1 - F_{L-1} at the deepest level L = 8) split each pair's
+// potential exactly; a level's force on body i is m_j (W - r W') (x_j - x_i) /
+// r^3, the exact gradient.
+//
+// A group's drift over the step h is M substeps of level 1.  A level-k
+// substep of length tau: kick with the level-k forces of the level's pairs for
+// tau / 2; the close-encounter test with radius R_k over tau on those pairs
+// (the flagged ones make up level k + 1); the level's bodies in no flagged
+// pair drift on their Kepler orbits for tau, the others take M substeps of
+// level k + 1; kick for tau / 2.  Level L tests nothing and drifts its
+// bodies.  The recursion runs as a loop over (level, substep) with the
+// pairs' levels in LDS.
+#include "symba_internal.h"
+#include "symba_kepler.h"
+
+#include <math.h>
+
+namespace symba {
+namespace {
+
+constexpr int kTableThreads = 1024;
+constexpr int kGroupThreads = 64;         // one wave per group
+constexpr int kGroupBlocks = 1024;        // workgroups of a group launch (each takes groups g, g + 1024, ...)
+constexpr int kEnds = 2 * kEncGroupBodies;  // pair endpoints of a group, padded to a power of two
+constexpr int kStatusEncSkipped = 4;      // SYMBA_STATUS_ENC_SKIPPED
+constexpr int kStatusCapacityBit = 1;     // SYMBA_STATUS_CAPACITY
+
+static_assert((kEnds & (kEnds - 1)) == 0, "the endpoint sort needs a power of two");
+static_assert((kEncMaxPairs & (kEncMaxPairs - 1)) == 0, "the table sort needs a power of two");
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// f_3 and its derivative at x clipped to [0, 1].
+__device__ __forceinline__ void partition(double x, double &f, double &df) {
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    const double x2 = x * x, x3 = x2 * x, u = 1.0 - x;
+    f = x3 * x * (35.0 - 84.0 * x + 70.0 * x2 - 20.0 * x3);
+    df = 140.0 * x3 * (u * u * u);
+}
+
+// F_k(r) and dF_k/dr; rk[j] = R_j of the pair.
+__device__ __forceinline__ void changeover(int k, double r, const double *rk, double &F, double &dF) {
+    if (k < 0) {
+        F = dF = 0.0;
+        return;
+    }
+    const double hi = rk[k], lo = rk[k + 1], w = hi - lo;
+    double f, df;
+    partition((r - lo) / w, f, df);
+    F = f;
+    dF = df / w;
+}
+
+// W - r W' of level k for a pair at separation r with critical radius r0.
+__device__ __forceinline__ double force_factor(int k, double r, double r0) {
+    double rk[kEncMaxLevel + 2];
+    rk[0] = r0;
+#pragma unroll
+    for (int j = 1; j < kEncMaxLevel + 2; ++j) rk[j] = rk[j - 1] / kEncShellRatio;
+    double w, dw;
+    if (k == kEncMaxLevel) {
+        double F, dF;
+        changeover(k - 1, r, rk, F, dF);
+        w = 1.0 - F;
+        dw = -dF;
+    } else {
+        double Fa, dFa, Fb, dFb;
+        changeover(k, r, rk, Fa, dFa);
+        changeover(k - 1, r, rk, Fb, dFb);
+        w = Fa - Fb;
+        dw = dFa - dFb;
+    }
+    return w - r * dw;
+}
+
+// The close-encounter test with radius `radius` over an interval tau (for tau
+// < 0 on the reversed motion): inside now, inside at the linearly
+// extrapolated end, or a closest approach inside the interval.
+__device__ __forceinline__ bool encounter(double dx, double dy, double dz, double wx, double wy, double wz,
+                                          double radius, double tau) {
+    if (tau < 0.0) {
+        wx = -wx;
+        wy = -wy;
+        wz = -wz;
+        tau = -tau;
+    }
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double v2 = wx * wx + wy * wy + wz * wz;
+    const double vr = dx * wx + dy * wy + dz * wz;
+    const double rc2 = radius * radius;
+    if (r2 < rc2) return true;
+    if (r2 + 2.0 * vr * tau + v2 * tau * tau < rc2) return true;
+    if (vr < 0.0 && -vr < v2 * tau) return r2 * v2 - vr * vr < rc2 * v2;
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Table of the groups of a pair list, by one workgroup: the pairs sorted by
+// (group label, pair index), so each group's pairs are contiguous and in the
+// pairs' order and the groups are in the order of their labels.
+
+__global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
+    __shared__ unsigned long long key[kEncMaxPairs];
+    __shared__ int wave_sum[kTableThreads / kWave];
+    const int tid = threadIdx.x;
+    const int64_t np64 = *e.n_pairs;
+    const int st = *e.status;
+    if ((st & kStatusCapacityBit) || np64 > e.pair_cap || np64 > kEncMaxPairs || np64 <= 0) {
+        if (tid == 0) {
+            e.ctl[kEncCtlGroups] = 0;
+            if (np64 > 0) e.ctl[kEncCtlSkipped] = 1;
+        }
+        return;
+    }
+    const int np = (int)np64;
+    int P2 = 1;
+    while (P2 < np) P2 <<= 1;
+    for (int t = tid; t < P2; t += kTableThreads)
+        key[t] = t < np ? ((unsigned long long)(unsigned)e.group_id[e.pair_i[t]] << 32) | (unsigned)t : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < P2; i += kTableThreads) {
+                const int o = i ^ j;
+                if (o > i) {
+                    const unsigned long long a = key[i], b = key[o];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[o] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // group starts in this thread's chunk (at most 8 entries), then their
+    // exclusive prefix over the threads
+    const int chunk = (np + kTableThreads - 1) / kTableThreads;
+    const int c0 = tid * chunk, c1 = min(c0 + chunk, np);
+    unsigned starts = 0;
+    int count = 0;
+    for (int t = c0; t < c1; ++t) {
+        const bool s = t == 0 || (key[t] >> 32) != (key[t - 1] >> 32);
+        starts |= (s ? 1u : 0u) << (t - c0);
+        count += s;
+    }
+    int incl = count;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int up = __shfl_up(incl, off);
+        if (lane() >= off) incl += up;
+    }
+    if (lane() == kWave - 1) wave_sum[tid / kWave] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int w = 0; w < kTableThreads / kWave; ++w) {
+        if (w < tid / kWave) base += wave_sum[w];
+        total += wave_sum[w];
+    }
+    int g = base + incl - count - 1;
+    for (int t = c0; t < c1; ++t) {
+        if ((starts >> (t - c0)) & 1u) {
+            ++g;
+            e.gstart[g] = t;
+        }
+        e.gp[t] = (int)(key[t] & 0xffffffffull);
+        key[t] = ((unsigned long long)(unsigned)g << 32) | (key[t] & 0xffffffffull);
+    }
+    if (tid == 0) {
+        e.gstart[total] = np;
+        e.ctl[kEncCtlGroups] = total;
+    }
+    __syncthreads();
+    // groups over the limit are left out (and reported); the others' bodies
+    // are marked for the drift kernels when asked
+    int over = 0;
+    for (int gg = tid; gg < total; gg += kTableThreads) {
+        const int big = (e.gstart[gg + 1] - e.gstart[gg]) > kEncGroupMaxPairs;
+        e.gskip[gg] = big;
+        over |= big;
+    }
+    if (__syncthreads_or(over) && tid == 0) e.ctl[kEncCtlSkipped] = 1;
+    if (e.mark) {
+        for (int t = tid; t < np; t += kTableThreads) {
+            const int gg = (int)(key[t] >> 32);
+            if (e.gstart[gg + 1] - e.gstart[gg] > kEncGroupMaxPairs) continue;
+            const int p = (int)(key[t] & 0xffffffffull);
+            e.ingroup[e.pair_i[p]] = 1;
+            e.ingroup[e.pair_j[p]] = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One group in a workgroup's LDS: its bodies (ascending global index) and its
+// pairs (the pairs' order) as local indices.
+
+struct GroupLds {
+    double x[kEncGroupBodies], y[kEncGroupBodies], z[kEncGroupBodies];
+    double vx[kEncGroupBodies], vy[kEncGroupBodies], vz[kEncGroupBodies];
+    double m[kEncGroupBodies], rc[kEncGroupBodies];
+    int body[kEncGroupBodies];       // global index of each local body
+    int pa[kEncGroupMaxPairs], pb[kEncGroupMaxPairs];  // local bodies of each pair (pa < pb globally)
+    int depth[kEncGroupMaxPairs];    // deepest level the pair is in
+    int ends[kEnds];
+    int nb, np;
+};
+
+// Loads group g: pair endpoints sorted and made unique (the bodies), pairs
+// mapped to local bodies, the bodies' state (positions when `full` is 0).
+// False (nothing loaded) when the pairs hold more bodies than fit, which a
+// pair list whose groups are its connected components never does.
+__device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
+    const int l = lane();
+    const int p0 = e.gstart[g], np = e.gstart[g + 1] - p0;
+    for (int t = l; t < kEnds / 2; t += kGroupThreads) {
+        int a = INT_MAX, b = INT_MAX;
+        if (t < np) {
+            const int p = e.gp[p0 + t];
+            a = e.pair_i[p];
+            b = e.pair_j[p];
+        }
+        G.ends[2 * t] = a;
+        G.ends[2 * t + 1] = b;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kEnds; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = l; i < kEnds; i += kGroupThreads) {
+                const int o = i ^ j;
+                if (o > i) {
+                    const int a = G.ends[i], b = G.ends[o];
+                    if ((a > b) == ((i & k) == 0)) {
+                        G.ends[i] = b;
+                        G.ends[o] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int nb = 0;
+    for (int base = 0; base < 2 * np; base += kGroupThreads) {
+        const int t = base + l;
+        const bool first = t < 2 * np && (t == 0 || G.ends[t] != G.ends[t - 1]);
+        const unsigned long long mask = __ballot(first);
+        const int pos = nb + __popcll(mask & ((1ull << l) - 1ull));
+        if (first && pos < kEncGroupBodies) G.body[pos] = G.ends[t];
+        nb += __popcll(mask);
+    }
+    __syncthreads();
+    if (nb > kEncGroupBodies) {
+        if (l == 0) e.ctl[kEncCtlSkipped] = 1;
+        return false;
+    }
+    for (int t = l; t < np; t += kGroupThreads) {
+        const int p = e.gp[p0 + t];
+        const int gi = e.pair_i[p], gj = e.pair_j[p];
+        int lo = 0, hi = nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (G.body[mid] < gi) lo = mid + 1; else hi = mid;
+        }
+        G.pa[t] = lo;
+        lo = 0;
+        hi = nb - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (G.body[mid] < gj) lo = mid + 1; else hi = mid;
+        }
+        G.pb[t] = lo;
+        G.depth[t] = 1;  // every pair of the group is flagged at level 0
+    }
+    for (int b = l; b < nb; b += kGroupThreads) {
+        const int k = G.body[b];
+        G.x[b] = e.x[k];
+        G.y[b] = e.y[k];
+        G.z[b] = e.z[k];
+        if (full) {
+            G.vx[b] = e.vx[k];
+            G.vy[b] = e.vy[k];
+            G.vz[b] = e.vz[k];
+        }
+        G.m[b] = k < e.n_tri ? e.m[k] : 0.0;
+        G.rc[b] = e.f * e.rh[k];
+    }
+    if (l == 0) {
+        G.nb = nb;
+        G.np = np;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Kick of level k for dt: each body's level-k pair forces summed in the
+// pairs' order, then v += dt a (bodies in no level-k pair are not touched).
+__device__ void kick(GroupLds &G, int k, double dt) {
+    const int nb = G.nb, np = G.np;
+    for (int b = lane(); b < nb; b += kGroupThreads) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        bool any = false;
+        for (int t = 0; t < np; ++t) {
+            if (G.depth[t] < k) continue;
+            const int i = G.pa[t], j = G.pb[t];
+            if (i != b && j != b) continue;
+            any = true;
+            const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double g = force_factor(k, r, G.rc[i] + G.rc[j]) / (r * r * r);
+            if (b == i) {
+                const double s = G.m[j] * g;
+                ax += s * dx;
+                ay += s * dy;
+                az += s * dz;
+            } else {
+                const double s = G.m[i] * g;
+                ax -= s * dx;
+                ay -= s * dy;
+                az -= s * dz;
+            }
+        }
+        if (any) {
+            G.vx[b] += dt * ax;
+            G.vy[b] += dt * ay;
+            G.vz[b] += dt * az;
+        }
+    }
+    __syncthreads();
+}
+
+// The test of level k over tau on the level's pairs: flagged pairs go to
+// level k + 1, the others stay at k.  Returns whether any was flagged.
+__device__ bool check(GroupLds &G, int k, double tau) {
+    bool any = false;
+    for (int t = lane(); t < G.np; t += kGroupThreads) {
+        if (G.depth[t] < k) continue;
+        const int i = G.pa[t], j = G.pb[t];
+        double radius = G.rc[i] + G.rc[j];
+        for (int q = 0; q < k; ++q) radius = radius / kEncShellRatio;
+        const bool fl = encounter(G.x[j] - G.x[i], G.y[j] - G.y[i], G.z[j] - G.z[i], G.vx[j] - G.vx[i],
+                                  G.vy[j] - G.vy[i], G.vz[j] - G.vz[i], radius, tau);
+        G.depth[t] = fl ? k + 1 : k;
+        any = any || fl;
+    }
+    return __syncthreads_or(any) != 0;
+}
+
+// Kepler drift for tau of the bodies whose deepest pair is at level k
+// (exactly k, or at least k when `at_least`).
+__device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
+    const int nb = G.nb, np = G.np;
+    for (int b = lane(); b < nb; b += kGroupThreads) {
+        int d = -1;
+        for (int t = 0; t < np; ++t)
+            if (G.pa[t] == b || G.pb[t] == b) d = max(d, G.depth[t]);
+        if (at_least ? d < k : d != k) continue;
+        double x = G.x[b], y = G.y[b], z = G.z[b], vx = G.vx[b], vy = G.vy[b], vz = G.vz[b];
+        kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
+        G.x[b] = x;
+        G.y[b] = y;
+        G.z[b] = z;
+        G.vx[b] = vx;
+        G.vy[b] = vy;
+        G.vz[b] = vz;
+    }
+    __syncthreads();
+}
+
+// The group's drift over h: M substeps of level 1, each recursing as deep as
+// its pairs need.  The loop visits (level, substep) in the order of the
+// recursion; every wave reaches its end after at most sum_k M^k substeps.
+__device__ void integrate(GroupLds &G, double h) {
+    int sub[kEncMaxLevel + 1];
+    int k = 1;
+    sub[1] = 0;
+    bool enter = true;
+    while (true) {
+        const double tau = ldexp(h, -2 * k);  // h / M^k, M = 4
+        if (enter) {
+            kick(G, k, 0.5 * tau);
+            if (k == kEncMaxLevel) {
+                drift(G, k, tau, true);
+                enter = false;
+            } else if (check(G, k, tau)) {
+                drift(G, k, tau, false);
+                ++k;
+                sub[k] = 0;
+            } else {
+                drift(G, k, tau, false);
+                enter = false;
+            }
+        } else {
+            kick(G, k, 0.5 * tau);
+            if (++sub[k] < kEncSub) {
+                enter = true;
+            } else if (k == 1) {
+                break;
+            } else {
+                --k;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kGroupThreads) void k_enc_groups(const EncDesc e) {
+    __shared__ GroupLds G;
+    const int ng = e.ctl[kEncCtlGroups];
+    for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+        if (e.gskip[g] || !load_group(e, G, g, true)) continue;
+        integrate(G, e.h);
+        for (int b = lane(); b < G.nb; b += kGroupThreads) {
+            const int k = G.body[b];
+            e.x[k] = G.x[b];
+            e.y[k] = G.y[b];
+            e.z[k] = G.z[b];
+            e.vx[k] = G.vx[b];
+            e.vy[k] = G.vy[b];
+            e.vz[k] = G.vz[b];
+            e.ingroup[k] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Level-0 reweighting of a group's accelerations: for each pair inside R_0,
+// m (F_0 - r F_0' - 1) (x_j - x_i) / r^3 on i and its opposite on j, summed
+// per body in the pairs' order and added to the Newtonian sums.
+__global__ __launch_bounds__(kGroupThreads) void k_enc_level0(const EncDesc e) {
+    __shared__ GroupLds G;
+    const int ng = e.ctl[kEncCtlGroups];
+    for (int g = blockIdx.x; g < ng; g += gridDim.x) {
+        if (e.gskip[g] || !load_group(e, G, g, false)) continue;
+        for (int b = lane(); b < G.nb; b += kGroupThreads) {
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            bool any = false;
+            for (int t = 0; t < G.np; ++t) {
+                const int i = G.pa[t], j = G.pb[t];
+                if (i != b && j != b) continue;
+                const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double r0 = G.rc[i] + G.rc[j];
+                if (r >= r0) continue;
+                any = true;
+                const double gf = (force_factor(0, r, r0) - 1.0) / (r * r * r);
+                if (b == i) {
+                    const double s = G.m[j] * gf;
+                    ax += s * dx;
+                    ay += s * dy;
+                    az += s * dz;
+                } else {
+                    const double s = G.m[i] * gf;
+                    ax -= s * dx;
+                    ay -= s * dy;
+                    az -= s * dz;
+                }
+            }
+            if (any) {
+                const int k = G.body[b];
+                e.ax[k] += ax;
+                e.ay[k] += ay;
+                e.az[k] += az;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The closing kick v += kick_h a of every body (when kick_h is not 0), and
+// the step's unresolved-pairs report ORed into the status.
+__global__ __launch_bounds__(256) void k_enc_kick(const EncDesc e) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e.kick_h != 0.0 && k < e.n) {
+        e.vx[k] = __builtin_fma(e.kick_h, e.ax[k], e.vx[k]);
+        e.vy[k] = __builtin_fma(e.kick_h, e.ay[k], e.vy[k]);
+        e.vz[k] = __builtin_fma(e.kick_h, e.az[k], e.vz[k]);
+    }
+    if (k == 0 && e.ctl[kEncCtlSkipped]) {
+        *e.status |= kStatusEncSkipped;
+        e.ctl[kEncCtlSkipped] = 0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_enc_table(const EncDesc &e, hipStream_t stream) {
+    hipLaunchKernelGGL(k_enc_table, dim3(1), dim3(kTableThreads), 0, stream, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_groups(const EncDesc &e, hipStream_t stream) {
+    hipLaunchKernelGGL(k_enc_groups, dim3(kGroupBlocks), dim3(kGroupThreads), 0, stream, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_level0(const EncDesc &e, hipStream_t stream) {
+    hipLaunchKernelGGL(k_enc_level0, dim3(kGroupBlocks), dim3(kGroupThreads), 0, stream, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_kick(const EncDesc &e, hipStream_t stream) {
+    const unsigned blocks = (unsigned)((e.n + 255) / 256);
+    hipLaunchKernelGGL(k_enc_kick, dim3(blocks), dim3(256), 0, stream, e);
+    return hipGetLastError();
+}
+
+}  // namespace symba

@@ -110,7 +110,56 @@ struct StepDesc {
     double kick_h, sun_h, kepler_h;     // h/2, h/2, h
     double *mom0, *mom1;                // [launch blocks][3] momentum partial sums (indexed by launch block)
     int64_t blk_base, nblk;             // this problem's blocks [blk_base, blk_base + nblk) of the launch
+    const int32_t *skip;                // [n] nonzero: no Kepler drift here (the encounter step), or null
 };
+
+// The encounter step (symba_step_enc): a table of the encounter groups built
+// from a pair list, the groups' integration through the shells, the level-0
+// reweighting of flagged pairs inside the critical radius and the closing
+// kick.  Limits: kEncMaxPairs flagged pairs per step, kEncGroupMaxPairs pairs
+// (so at most kEncGroupMaxPairs + 1 bodies) per group.
+constexpr int kEncMaxPairs = 8192;
+constexpr int kEncGroupMaxPairs = 255;
+constexpr int kEncGroupBodies = kEncGroupMaxPairs + 1;
+constexpr int kEncMaxLevel = 8;       // deepest level
+constexpr int kEncSub = 4;            // substeps per level
+constexpr double kEncShellRatio = 2.08;
+constexpr int kEncCtlGroups = 0;      // ctl[]: groups of the current table
+constexpr int kEncCtlSkipped = 1;     // ctl[]: nonzero when pairs went unresolved this step
+constexpr int kEncCtlInts = 4;
+
+struct EncDesc {
+    double *x, *y, *z, *vx, *vy, *vz;   // state (device, n), updated in place
+    const double *m, *rh;
+    double *ax, *ay, *az;               // accelerations (the caller's outputs)
+    int64_t n, n_tri;                   // bodies; massive bodies [0, n_tri)
+    double f;                           // critical-radius factor: R_0 = f (rh_i + rh_j)
+    double h;                           // the step
+    double kick_h;                      // the closing kick (0: none)
+    // the pair list the table is built from (the caller's outputs)
+    const int32_t *pair_i, *pair_j;
+    const int64_t *n_pairs;
+    int32_t *status;
+    const int32_t *group_id;
+    int64_t pair_cap;
+    // scratch (context-owned)
+    int32_t *gp;      // [kEncMaxPairs] pair indices grouped by group, each group's in the pairs' order
+    int32_t *gstart;  // [kEncMaxPairs + 1] first entry of each group in gp
+    int32_t *gskip;   // [kEncMaxPairs] 1: the group is larger than the limit (not resolved)
+    int32_t *ctl;     // [kEncCtlInts]
+    int32_t *ingroup; // [n] 1 for bodies of resolved groups while the step runs, zero between calls
+    int mark;         // 1: the table marks ingroup (the table at the step's start)
+};
+
+// Encounter-step launches (csrc/symba_enc.hip) and the drifts of the
+// encounter step around them (csrc/symba_step.hip): first kick, table of the
+// step's groups, Sun drift and Kepler drift of the other bodies, the groups'
+// integration, momentum, Sun drift.
+hipError_t launch_enc_table(const EncDesc &e, hipStream_t stream);
+hipError_t launch_enc_groups(const EncDesc &e, hipStream_t stream);
+hipError_t launch_enc_level0(const EncDesc &e, hipStream_t stream);
+hipError_t launch_enc_kick(const EncDesc &e, hipStream_t stream);
+hipError_t launch_drifts_enc(const StepDesc &one, const EncDesc &enc, hipStream_t stream);
 
 // Blocks of the drift kernels for n bodies, and their launch (first kick,
 // Sun drift, Kepler drift, Sun drift): one problem (`one`, list null) or the

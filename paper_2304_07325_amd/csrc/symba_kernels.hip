@@ -1478,9 +1478,9 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
             d.az[k] = sz;
         }
         if (d.kvx) {  // the step's closing half kick
-            d.kvx[k] += d.kick_h * sx;
-            d.kvy[k] += d.kick_h * sy;
-            d.kvz[k] += d.kick_h * sz;
+            d.kvx[k] = __builtin_fma(d.kick_h, sx, d.kvx[k]);
+            d.kvy[k] = __builtin_fma(d.kick_h, sy, d.kvy[k]);
+            d.kvz[k] = __builtin_fma(d.kick_h, sz, d.kvz[k]);
         }
         nonfinite = !(isfinite(sx) && isfinite(sy) && isfinite(sz));
         // group label = union-find root, the smallest index of the component

@@ -16,6 +16,7 @@
 // same order), so every block sees the same bits and the step is
 // reproducible.
 #include "symba_internal.h"
+#include "symba_kepler.h"
 
 #include <math.h>
 
@@ -70,102 +71,6 @@ __device__ __forceinline__ void read_momentum(const StepDesc &s, const double *p
     pz = block_sum(c, red);
 }
 
-// Coefficients of the Stumpff series: 1/(2k+2)! and 1/(2k+3)!, k = 0 ..
-// kStumpffTerms - 1, computed at compile time.  For |x| < 1 the first
-// omitted terms, 1/24! and 1/25!, are below 2^-53 of c2 and c3.
-constexpr int kStumpffTerms = 11;
-struct StumpffCoeffs {
-    double c2[kStumpffTerms], c3[kStumpffTerms];
-};
-constexpr StumpffCoeffs make_stumpff_coeffs() {
-    StumpffCoeffs t{};
-    double f = 2.0;  // (2k+2)!
-    for (int k = 0; k < kStumpffTerms; ++k) {
-        t.c2[k] = 1.0 / f;
-        f *= 2.0 * k + 3.0;
-        t.c3[k] = 1.0 / f;
-        f *= 2.0 * k + 4.0;
-    }
-    return t;
-}
-constexpr StumpffCoeffs kStumpff = make_stumpff_coeffs();
-
-// Stumpff functions c0..c3 of x (Danby, Fundamentals of Celestial Mechanics,
-// Sec. 6.9): c0 = cos sqrt x, c1 = sin sqrt x / sqrt x, c2 = (1 - cos sqrt x) / x,
-// c3 = (sqrt x - sin sqrt x) / sqrt(x)^3, continued through x <= 0.  Near 0
-// the series of c2 and c3 (terms (-x)^k / (2k+2)! and (-x)^k / (2k+3)!) in
-// Horner form, one FMA per term with no division on the solver's critical
-// path, then c0 = 1 - x c2 and c1 = 1 - x c3.
-__device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double &c2, double &c3) {
-    if (fabs(x) < 1.0) {
-        const double y = -x;
-        double s2 = kStumpff.c2[kStumpffTerms - 1], s3 = kStumpff.c3[kStumpffTerms - 1];
-#pragma unroll
-        for (int k = kStumpffTerms - 2; k >= 0; --k) {
-            s2 = __builtin_fma(s2, y, kStumpff.c2[k]);
-            s3 = __builtin_fma(s3, y, kStumpff.c3[k]);
-        }
-        c2 = s2;
-        c3 = s3;
-        c0 = 1.0 - x * c2;
-        c1 = 1.0 - x * c3;
-    } else if (x > 0.0) {
-        const double q = sqrt(x), sn = sin(q), cs = cos(q);
-        c0 = cs;
-        c1 = sn / q;
-        c2 = (1.0 - cs) / x;
-        c3 = (q - sn) / (x * q);
-    } else {
-        const double q = sqrt(-x), sn = sinh(q), cs = cosh(q);
-        c0 = cs;
-        c1 = sn / q;
-        c2 = (cs - 1.0) / -x;
-        c3 = (sn - q) / (-x * q);
-    }
-}
-
-// Two-body drift about a centre of gravitational parameter 1 for time h, in
-// Danby's universal variable s: r0 s c1 + eta s^2 c2 + s^3 c3 = h with
-// beta = 2 / r0 - |v|^2, eta = x . v and the c's at beta s^2, solved by the
-// Laguerre-Conway iteration (Conway 1986), then the f and g functions
-// f = 1 - s^2 c2 / r0, g = h - s^3 c3, fdot = -s c1 / (r r0), gdot = 1 - s^2 c2 / r.
-__device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, double &vx, double &vy, double &vz,
-                                             double h) {
-    const double r0 = sqrt(x * x + y * y + z * z);
-    const double beta = 2.0 / r0 - (vx * vx + vy * vy + vz * vz);
-    const double eta = x * vx + y * vy + z * vz;
-    const double zeta = 1.0 - beta * r0;
-    // first guess: h / r0 for short arcs and ellipses; on a hyperbola the
-    // variable grows like log(v_inf t) / v_inf (r ~ v_inf t far out)
-    double s = h / r0, c0, c1, c2, c3;
-    if (beta < 0.0) {
-        const double vinf = sqrt(-beta);
-        s = copysign(log1p(vinf * fabs(h) / r0) / vinf, h);
-    }
-    for (int it = 0; it < 40; ++it) {
-        stumpff(beta * s * s, c0, c1, c2, c3);
-        const double F = s * (r0 * c1 + s * (eta * c2 + s * c3)) - h;
-        const double dF = r0 * c0 + s * (eta * c1 + s * c2);
-        const double ddF = eta * c0 + zeta * s * c1;
-        const double root = sqrt(fabs(16.0 * dF * dF - 20.0 * F * ddF));
-        const double ds = -5.0 * F / (dF + (dF >= 0.0 ? root : -root));
-        s += ds;
-        if (!(fabs(ds) > 1e-15 * fabs(s))) break;  // converged (or NaN input)
-    }
-    stumpff(beta * s * s, c0, c1, c2, c3);
-    const double r = r0 * c0 + s * (eta * c1 + s * c2);
-    const double inv_r0 = 1.0 / r0, inv_r = 1.0 / r;
-    const double f = 1.0 - s * s * c2 * inv_r0, g = h - s * s * s * c3;
-    const double fd = -s * c1 * inv_r0 * inv_r, gd = 1.0 - s * s * c2 * inv_r;
-    const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
-    vx = fd * x + gd * vx;
-    vy = fd * y + gd * vy;
-    vz = fd * z + gd * vz;
-    x = nx;
-    y = ny;
-    z = nz;
-}
-
 // The problem of launch block b: `one`, or the last of the list whose first
 // block is not above b.
 template <bool LIST>
@@ -201,8 +106,9 @@ __device__ __forceinline__ void kick_momentum(const StepDesc &s, double &px, dou
     write_momentum(s, s.mom0, k, vx, vy, vz, px, py, pz);
 }
 
-// x += sun_h P (P = p* on entry), Kepler drift for kepler_h, then the new
-// momentum partial sum (returned in p*).
+// x += sun_h P (P = p* on entry), Kepler drift for kepler_h (not for the
+// bodies that `skip` marks: the encounter-group integrator moves them), then
+// the new momentum partial sum (returned in p*).
 __device__ __forceinline__ void sun_kepler(const StepDesc &s, double &px, double &py, double &pz) {
     const int64_t k = body_of(s);
     double vx = 0.0, vy = 0.0, vz = 0.0;
@@ -211,7 +117,7 @@ __device__ __forceinline__ void sun_kepler(const StepDesc &s, double &px, double
         vx = s.vx[k];
         vy = s.vy[k];
         vz = s.vz[k];
-        kepler_drift(x, y, z, vx, vy, vz, s.kepler_h);
+        if (!s.skip || !s.skip[k]) kepler::kepler_drift(x, y, z, vx, vy, vz, s.kepler_h);
         s.x[k] = x;
         s.y[k] = y;
         s.z[k] = z;
@@ -256,6 +162,20 @@ __global__ __launch_bounds__(kStepThreads) void k_sun(const StepDesc one, const 
     sun(s, px, py, pz);
 }
 
+// The momentum partial sums after the drifts, from the velocities in memory
+// (the encounter step: its group integrator moves some bodies after
+// k_sun_kepler).  The same sums, in the same order, as k_sun_kepler's.
+__global__ __launch_bounds__(kStepThreads) void k_momentum(const StepDesc one) {
+    const int64_t k = body_of(one);
+    double vx = 0.0, vy = 0.0, vz = 0.0, px, py, pz;
+    if (k < one.n) {
+        vx = one.vx[k];
+        vy = one.vy[k];
+        vz = one.vz[k];
+    }
+    write_momentum(one, one.mom1, k, vx, vy, vz, px, py, pz);
+}
+
 // All three for a problem of one block (n <= kStepThreads), in one launch:
 // each thread reads back only its own body, and the momentum is the block's
 // own sum, which is exactly what reading back the one partial would give
@@ -270,6 +190,17 @@ __global__ __launch_bounds__(kStepThreads) void k_drifts_block(const StepDesc on
 }  // namespace
 
 int64_t step_blocks(int64_t n) { return (n + kStepThreads - 1) / kStepThreads; }
+
+hipError_t launch_drifts_enc(const StepDesc &one, const EncDesc &enc, hipStream_t stream) {
+    const unsigned blocks = (unsigned)one.nblk;
+    hipLaunchKernelGGL(k_kick_momentum<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, nullptr, 0);
+    if (launch_enc_table(enc, stream) != hipSuccess) return hipErrorUnknown;
+    hipLaunchKernelGGL(k_sun_kepler<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, nullptr, 0);
+    if (launch_enc_groups(enc, stream) != hipSuccess) return hipErrorUnknown;
+    hipLaunchKernelGGL(k_momentum, dim3(blocks), dim3(kStepThreads), 0, stream, one);
+    hipLaunchKernelGGL(k_sun<false>, dim3(blocks), dim3(kStepThreads), 0, stream, one, nullptr, 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_drifts(const StepDesc &one, const StepDesc *list, int n_list, int64_t total_blocks,
                          hipStream_t stream) {

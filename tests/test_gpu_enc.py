@@ -1,0 +1,257 @@
+"""symba_step_enc (GPU) against the encounter-step oracle: one step at a time
+from the oracle's own inputs (state, level-0 accelerations, flagged pairs),
+so rounding differences cannot grow over many steps, on a fast flyby through
+several shells, three separate flybys (three groups in parallel), a
+crowded cluster (a group of 89 pairs) and a cold disk with nothing flagged (bit-identical to symba_step); the status bit
+and the plain step for a group over the size limit; time reversal on the
+device."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import symba_enc as E
+from paper_2304_07325_amd import diskgen as dg
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+F = 3.0
+KEYS = ("x", "y", "z", "vx", "vy", "vz")
+# One step's positions and velocities agree to 1e-11 of their scale: both
+# sides compute in FP64, the device with fused multiply-adds and its own
+# Kepler solver (Laguerre-Conway on Danby's variable against Newton on
+# Curtis' universal anomaly, each converged to ~1e-15), through up to a few
+# hundred substeps, each a few ulp, amplified by the encounter's shear.
+STATE_TOL = 1e-11
+ACC_TOL = 1e-11
+
+
+def _state(x, v_helio, m):
+    x, v, m = (np.asarray(a, dtype=np.float64) for a in (x, v_helio, m))
+    vb = v - (m[:, None] * v).sum(0) / (1.0 + m.sum())
+    rh = (m / 3.0) ** (1.0 / 3.0) * np.linalg.norm(x, axis=1)
+    return dict(x=x[:, 0].copy(), y=x[:, 1].copy(), z=x[:, 2].copy(), vx=vb[:, 0].copy(), vy=vb[:, 1].copy(),
+                vz=vb[:, 2].copy(), m=m.copy(), rh=rh)
+
+
+def _flyby(phase=0.0, b=0.003, vrel=0.3, sep=0.3, mA=1e-4, mB=3e-5):
+    c, s = math.cos(phase), math.sin(phase)
+    rot = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    x = np.array([[1.0, 0.0, 0.0], [1.0 + b, -sep, 0.0]]) @ rot.T
+    v = np.array([[0.0, 1.0, 0.0], [0.0, 1.0 + vrel, 0.0]]) @ rot.T
+    return x, v, np.array([mA, mB])
+
+
+class Dev:
+    """A device state and outputs on one context."""
+
+    def __init__(self, n, pair_cap=None):
+        import torch
+        from paper_2304_07325_amd import binding as B
+        self.B, self.torch, self.n = B, torch, n
+        self.ctx = B.Context(max_n=max(n, 64), max_pairs=1 << 16)
+        self.out = B.Outputs(n, pair_cap or max(4 * n, 4096))
+
+    def load(self, s, acc=None, pairs=None, ora=None):
+        """Uploads state s; with acc and pairs, also the outputs a step reads
+        (level-0 accelerations, pairs, their groups, status 0)."""
+        t = self.torch
+        self.st = self.B.to_device_state(s)
+        if acc is not None:
+            pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+            gid, ng = ora.groups(self.n, pairs[:, 0], pairs[:, 1])
+            self.out.acc.copy_(t.from_numpy(np.ascontiguousarray(acc.T)))
+            k = len(pairs)
+            self.out.pair_i[:k].copy_(t.from_numpy(pairs[:, 0].astype(np.int32)))
+            self.out.pair_j[:k].copy_(t.from_numpy(pairs[:, 1].astype(np.int32)))
+            self.out.scalars64.fill_(k)
+            self.out.group_id.copy_(t.from_numpy(gid))
+            self.out.scalars32.copy_(t.tensor([ng, 0], dtype=t.int32))
+
+    def state(self):
+        self.torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in self.st.items()}
+
+    def close(self):
+        self.ctx.close()
+
+
+def _compare_step(dev, ora, s, n_m, h, acc, pairs):
+    """One device step from the oracle's inputs against the oracle's step."""
+    want, acc_w, pairs_w = E.step(s, n_m, h, F, acc, pairs, ora=ora)
+    dev.load(s, acc, pairs, ora)
+    dev.ctx.step_enc(dev.st, n_m, h, F, dev.out)
+    got = dev.state()
+    out = dev.out.to_host()
+    for k in KEYS:
+        scale = np.abs(want[k]).max() + (1.0 if k in ("x", "y", "z") else 0.0)
+        assert np.abs(got[k] - want[k]).max() <= STATE_TOL * scale, (k, np.abs(got[k] - want[k]).max())
+    assert out["status"] == 0
+    assert np.array_equal(np.stack([out["pair_i"], out["pair_j"]], 1), pairs_w)
+    # measured against the Newtonian sums: deep inside R_0 the level-0 force
+    # of a pair is zero, and its accelerations cancel to rounding
+    scale = np.abs(ora.accel(want, n_m)).max()
+    assert np.abs(out["acc"] - acc_w).max() <= ACC_TOL * scale
+    return want, acc_w, pairs_w
+
+
+@pytest.fixture(scope="module")
+def ora():
+    return oracle.default()
+
+
+def test_flyby_step_by_step(ora):
+    x, v, m = _flyby()
+    s = _state(x, v, m)
+    h = 0.025
+    acc, pairs = E.prepare(s, 2, h, F, ora=ora)
+    dev = Dev(2)
+    G.say("flyby, 40 steps")
+    deepest = 0
+    for k in range(40):
+        s, acc, pairs = _compare_step(dev, ora, s, 2, h, acc, pairs)
+        d = np.linalg.norm([s["x"][1] - s["x"][0], s["y"][1] - s["y"][0]])
+        r0 = F * s["rh"].sum()
+        while deepest < E.L_MAX and d < E.shell_radius(r0, deepest + 1):
+            deepest += 1
+    assert deepest >= 3   # the flyby went through several shells
+    dev.close()
+
+
+def test_three_groups_in_parallel(ora):
+    xs, vs, ms = zip(*(_flyby(phase=p, sep=0.15) for p in (0.0, 2.1, 4.2)))
+    s = _state(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+    h = 0.025
+    acc, pairs = E.prepare(s, 6, h, F, ora=ora)
+    dev = Dev(6)
+    G.say("three flybys, 16 steps")
+    for _ in range(16):
+        assert len(pairs) == 3
+        s, acc, pairs = _compare_step(dev, ora, s, 6, h, acc, pairs)
+    dev.close()
+
+
+def _cluster(n=40, spread=0.08, seed=12):
+    """A crowded patch of Earth-mass bodies near 1 AU: 90 flagged pairs in a
+    group of 89 pairs and one of 1."""
+    rng = np.random.default_rng(seed)
+    x = np.c_[1.0 + rng.normal(0, spread, n), rng.normal(0, spread, n), rng.normal(0, spread / 5, n)]
+    r = np.linalg.norm(x[:, :2], axis=1)
+    v = np.c_[-x[:, 1], x[:, 0], np.zeros(n)] / r[:, None] ** 1.5 + rng.normal(0, 0.01, (n, 3))
+    return _state(x, v, np.full(n, 3e-6))
+
+
+def test_crowded_cluster(ora):
+    """Groups of many pairs (89 and 1), each resolved by one workgroup."""
+    s = _cluster()
+    n = s["x"].size
+    h = 0.01
+    acc, pairs = E.prepare(s, n, h, F, ora=ora)
+    assert len(pairs) >= 60
+    dev = Dev(n)
+    G.say("crowded cluster, 5 steps")
+    for _ in range(5):
+        s, acc, pairs = _compare_step(dev, ora, s, n, h, acc, pairs)
+    dev.close()
+
+
+def test_prepare_matches_the_oracle(ora):
+    s = _cluster()
+    n = s["x"].size
+    h = 0.01
+    acc, pairs = E.prepare(s, n, h, F, ora=ora)
+    dev = Dev(n)
+    dev.load(s)
+    dev.ctx.enc_prepare(dev.st, n, h, F, dev.out)
+    out = dev.out.to_host()
+    assert np.array_equal(np.stack([out["pair_i"], out["pair_j"]], 1), pairs)
+    assert np.abs(out["acc"] - acc).max() <= ACC_TOL * np.abs(ora.accel(s, n)).max()
+    assert out["status"] == 0
+    # the reweighting changed what the plain evaluation gives
+    plain = ora.kick_encounter(s, n, h, F)["acc"]
+    assert np.abs(out["acc"] - plain).max() > 1e-6 * np.abs(plain).max()
+    dev.close()
+
+
+def _cold_ring(n=60, seed=5):
+    rng = np.random.default_rng(seed)
+    a = np.sort(rng.uniform(5.0, 20.0, n))
+    th = rng.uniform(0, 2 * np.pi, n)
+    x = np.c_[a * np.cos(th), a * np.sin(th), np.zeros(n)]
+    v = np.c_[-np.sin(th), np.cos(th), np.zeros(n)] / np.sqrt(a)[:, None]
+    return _state(x, v, np.full(n, 1e-9))
+
+
+def test_nothing_flagged_is_the_plain_step_bitwise():
+    s = _cold_ring()
+    n = s["x"].size
+    h = 0.5 * dg.YEAR
+    plain, enc = Dev(n), Dev(n)
+    plain.load(s)
+    enc.load(s)
+    plain.ctx.kick_encounter(plain.st, n, abs(h), F, out=plain.out)
+    enc.ctx.enc_prepare(enc.st, n, h, F, enc.out)
+    G.say("cold ring, 4 steps, plain vs encounter step")
+    for _ in range(4):
+        plain.ctx.step(plain.st, n, h, F, plain.out)
+        enc.ctx.step_enc(enc.st, n, h, F, enc.out)
+        a, b = plain.state(), enc.state()
+        assert plain.out.to_host()["n_pairs"] == 0 and enc.out.to_host()["n_pairs"] == 0
+        for k in KEYS:
+            assert a[k].tobytes() == b[k].tobytes(), k
+        assert plain.out.to_host()["acc"].tobytes() == enc.out.to_host()["acc"].tobytes()
+    plain.close()
+    enc.close()
+
+
+def test_group_over_the_limit_takes_the_plain_step():
+    """A tight cluster whose one group has more than 255 pairs: the status
+    reports it and the step is the plain step, bit for bit."""
+    rng = np.random.default_rng(11)
+    n = 40
+    x = np.c_[1.0 + rng.normal(0, 0.01, n), rng.normal(0, 0.01, n), rng.normal(0, 0.002, n)]
+    v = np.c_[-x[:, 1], x[:, 0], np.zeros(n)]
+    s = _state(x, v, np.full(n, 3e-6))
+    h = 0.01
+    plain, enc = Dev(n), Dev(n)
+    plain.load(s)
+    enc.load(s)
+    plain.ctx.kick_encounter(plain.st, n, abs(h), F, out=plain.out)
+    enc.ctx.enc_prepare(enc.st, n, h, F, enc.out)
+    first = enc.out.to_host()
+    assert first["n_pairs"] > 255 and first["n_groups"] == 1
+    assert first["status"] & enc.B.STATUS_ENC_SKIPPED
+    plain.ctx.step(plain.st, n, h, F, plain.out)
+    enc.ctx.step_enc(enc.st, n, h, F, enc.out)
+    a, b = plain.state(), enc.state()
+    for k in KEYS:
+        assert a[k].tobytes() == b[k].tobytes(), k
+    assert enc.out.to_host()["status"] & enc.B.STATUS_ENC_SKIPPED
+    plain.close()
+    enc.close()
+
+
+def test_time_reversal_on_the_device():
+    x, v, m = _flyby(sep=0.12)
+    s = _state(x, v, m)
+    h = 0.025
+    dev = Dev(2)
+    dev.load(s)
+    dev.ctx.enc_prepare(dev.st, 2, h, F, dev.out)
+    for _ in range(20):
+        dev.ctx.step_enc(dev.st, 2, h, F, dev.out)
+    mid = dev.state()
+    for k in ("vx", "vy", "vz"):
+        dev.st[k].neg_()
+    dev.ctx.enc_prepare(dev.st, 2, h, F, dev.out)
+    for _ in range(20):
+        dev.ctx.step_enc(dev.st, 2, h, F, dev.out)
+    back = dev.state()
+    assert np.abs(mid["x"] - s["x"]).max() > 0.05   # it moved
+    for k in ("x", "y", "z"):
+        assert np.abs(back[k] - s[k]).max() < 1e-11, k
+    for k in ("vx", "vy", "vz"):
+        assert np.abs(-back[k] - s[k]).max() < 1e-11, k
+    dev.close()
