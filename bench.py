@@ -343,17 +343,37 @@ def bench_step(args, B, dg, torch):
                           "pairs_per_s": dg.pair_count(n, n_m) / sec, "steps": steps}
     log(f"step {args.workload}: {1.0 / sec:.0f} steps/s, {sec * 1e3:.4f} ms/step")
     ctx.close()
-    # the accuracy test
+    # the accuracy test, with the plain step and with the encounter step
     acc_disk = dg.make_accuracy_disk(n=100)
+    res["accuracy_disk"] = accuracy_run(args, B, dg, torch, acc_disk, encounters=False)
+    res["accuracy_disk_enc"] = accuracy_run(args, B, dg, torch, acc_disk, encounters=True)
+    return res
+
+
+def accuracy_run(args, B, dg, torch, acc_disk, encounters):
+    """The paper's accuracy test (Sec. 3): the 100-body disk integrated for
+    `--accuracy-years` in 0.1-year steps, with the relative energy and
+    angular-momentum errors at 50 checkpoints.  encounters: the encounter
+    step (symba_step_enc: groups through the shells) instead of the plain
+    step (every pair a full-strength kick)."""
+    import numpy as np
+    f = dg.RCRIT_FACTOR
     s0 = acc_disk.state(0)
     nm, h = acc_disk.n_massive, acc_disk.dt
     total = int(round(args.accuracy_years * dg.YEAR / h))
-    st = B.to_device_state(s0)
-    ctx = B.Context(max_n=128, max_pairs=1 << 14)
-    out = B.Outputs(100, 1 << 13)
-    ctx.kick_encounter(st, nm, h, f, out=out)
-    torch.cuda.synchronize()
-    ctx.read_stats()
+    label = "encounter step" if encounters else "plain step"
+
+    def start(st, ctx, out):
+        if encounters:
+            ctx.enc_prepare(st, nm, h, f, out)
+        else:
+            ctx.kick_encounter(st, nm, h, f, out=out)
+
+    def step(st, ctx, out, stream=None):
+        if encounters:
+            ctx.step_enc(st, nm, h, f, out, stream=stream)
+        else:
+            ctx.step(st, nm, h, f, out, stream=stream)
 
     def invariants(s):
         """Energy of the split Hamiltonian (Kepler + Sun + interaction terms,
@@ -375,28 +395,34 @@ def bench_step(args, B, dg, torch):
     st_e = B.to_device_state(s0)
     ctx_e = B.Context(max_n=128, max_pairs=1 << 14)
     out_e = B.Outputs(100, 1 << 13)
-    ctx_e.kick_encounter(st_e, nm, h, f, out=out_e)
+    start(st_e, ctx_e, out_e)
     for _ in range(20):
-        ctx_e.step(st_e, nm, h, f, out_e)
+        step(st_e, ctx_e, out_e)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(eager_n):
-        ctx_e.step(st_e, nm, h, f, out_e)
+        step(st_e, ctx_e, out_e)
     torch.cuda.synchronize()
     eager_rate = eager_n / (time.perf_counter() - t0)
     ctx_e.close()
     # the run itself: graphs of graph_steps steps (the same bits as eager
     # steps), the remainder of each chunk eager
+    st = B.to_device_state(s0)
+    ctx = B.Context(max_n=128, max_pairs=1 << 14)
+    out = B.Outputs(100, 1 << 13)
+    start(st, ctx, out)   # also sizes the context's scratch for the captured steps
+    torch.cuda.synchronize()
+    ctx.read_stats()
     graph_steps = 100
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
-    graph = torch.cuda.CUDAGraph()
+    graph = torch.cuda.CUDAGraph()   # capturing runs nothing: the run starts at s0
     with torch.cuda.graph(graph, stream=side):
         for _ in range(graph_steps):
-            ctx.step(st, nm, h, f, out, stream=side)
+            step(st, ctx, out, stream=side)
     torch.cuda.synchronize()
     e0, L0 = invariants(s0)
-    chunks, worst_e, worst_l = 50, 0.0, 0.0
+    chunks, worst_e, worst_l, skipped = 50, 0.0, 0.0, 0
     per = max(total // chunks, 1)
     t0 = time.perf_counter()
     done = 0
@@ -405,26 +431,29 @@ def bench_step(args, B, dg, torch):
         for _ in range(k // graph_steps):
             graph.replay()
         for _ in range(k % graph_steps):
-            ctx.step(st, nm, h, f, out)
+            step(st, ctx, out)
         done += k
         torch.cuda.synchronize()
         cur = {key: v.cpu().numpy() for key, v in st.items()}
         e, L = invariants(cur)
         worst_e = max(worst_e, abs(e - e0) / abs(e0))
         worst_l = max(worst_l, float(np.linalg.norm(L - L0) / np.linalg.norm(L0)))
+        skipped += bool(out.to_host()["status"] & B.STATUS_ENC_SKIPPED)
     wall = time.perf_counter() - t0
     _, flagged, calls = ctx.read_stats()
-    res["accuracy_disk"] = {"n": 100, "step_years": h / dg.YEAR, "years": done * h / dg.YEAR, "steps": done,
-                            "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
-                            "angmom_rel_err_max": worst_l, "checkpoints": chunks,
-                            "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
-                            "steps_per_s": done / wall, "graph_steps": graph_steps,
-                            "eager_steps_per_s": eager_rate}
-    log(f"accuracy disk: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s ({done / wall:.0f} steps/s "
-        f"in graphs of {graph_steps}, {eager_rate:.0f} eager), energy err max "
+    r = {"n": 100, "step_years": h / dg.YEAR, "years": done * h / dg.YEAR, "steps": done,
+         "stepper": "symba_step_enc" if encounters else "symba_step",
+         "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
+         "angmom_rel_err_max": worst_l, "checkpoints": chunks,
+         "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
+         "steps_per_s": done / wall, "graph_steps": graph_steps, "eager_steps_per_s": eager_rate}
+    if encounters:
+        r["checkpoints_with_unresolved_pairs"] = skipped
+    log(f"accuracy disk, {label}: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s ({done / wall:.0f} "
+        f"steps/s in graphs of {graph_steps}, {eager_rate:.0f} eager), energy err max "
         f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}")
     ctx.close()
-    return res
+    return r
 
 
 def bench_other_workloads(args, B, dg, torch):

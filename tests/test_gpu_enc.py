@@ -255,3 +255,42 @@ def test_time_reversal_on_the_device():
     for k in ("vx", "vy", "vz"):
         assert np.abs(-back[k] - s[k]).max() < 1e-11, k
     dev.close()
+
+
+def test_graph_replays_match_eager_steps():
+    """Encounter steps captured into a graph: each replay gives the bits of the
+    same number of eager steps (run on a second context and state), with
+    eager work on the captured context between the replays."""
+    import torch
+    x, v, m = _flyby(sep=0.15)   # inside the critical radius for all nine steps
+    s = _state(x, v, m)
+    h = 0.025
+    eager, graphed = Dev(2), Dev(2)
+    eager.load(s)
+    graphed.load(s)
+    eager.ctx.enc_prepare(eager.st, 2, h, F, eager.out)
+    graphed.ctx.enc_prepare(graphed.st, 2, h, F, graphed.out)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(3):
+            graphed.ctx.step_enc(graphed.st, 2, h, F, graphed.out, stream=side)
+    torch.cuda.synchronize()
+    other = Dev(2)
+    for rep in range(3):
+        graph.replay()
+        for _ in range(3):
+            eager.ctx.step_enc(eager.st, 2, h, F, eager.out)
+        # eager work on the captured context in between
+        other.load(s)
+        graphed.ctx.enc_prepare(other.st, 2, h, F, other.out)
+        torch.cuda.synchronize()
+        a, b = eager.state(), graphed.state()
+        for k in KEYS:
+            assert a[k].tobytes() == b[k].tobytes(), (rep, k)
+        ea, ga = eager.out.to_host(), graphed.out.to_host()
+        assert ea["acc"].tobytes() == ga["acc"].tobytes() and ea["n_pairs"] == ga["n_pairs"] == 1
+    for d in (eager, graphed, other):
+        d.close()
