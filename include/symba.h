@@ -308,11 +308,12 @@ int symba_step_batch(symba_ctx *ctx, const symba_step_problem *steps, int32_t n_
 
 /* Host-only helper (no device work): the task list of the folded trapezoid
  * for n, n_m and a tile size of 64*rows bodies, in the order a single call
- * launches them (field blocks first, then the folded triangle's whole block
+ * launches them (field tasks first, then the folded triangle's whole block
  * pairs, row by row, then the 64 x 64 tile pairs of the block pairs that are
  * split so that the launch ends with short tasks).  Writes up to cap tasks as
  * (kind, a, b) triples into tasks[3*k..3*k+2] (kind 0: triangle block pair
- * (a, b) in units of 64*rows; kind 1: field block a against all massive rows;
+ * (a, b) in units of 64*rows; kind 1: field block a (64*field_rows field
+ * bodies) against segment b of the massive rows, rows [192 b, 192 b + 192);
  * kind 2: triangle tile pair (a, b) in units of 64 bodies) and returns the
  * task count, or -1 on invalid arguments. */
 int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_rows,

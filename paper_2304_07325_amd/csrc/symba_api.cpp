@@ -159,6 +159,7 @@ int split_for(const symba_ctx *c, int64_t n_tri, int rows) {
 
 struct Plan {
     int64_t n_rows, n_tri, B, n_split, n_whole, n_slots, n_tri_tasks, n_field_tasks, n_blk;
+    int64_t n_fblocks, n_fslots;  // field blocks; segments of the massive rows per field block
     int rows;
     size_t partial_doubles;
 };
@@ -178,10 +179,12 @@ Plan make_plan(int64_t n, int64_t n_m, int rows, int field_rows, int split) {
         p.n_whole = symba::whole_count(p.B, p.n_split);
         p.n_tri_tasks = p.n_whole + p.n_split * p.B * rows * rows;
         p.n_slots = symba::partial_slots(p.B, rows, p.n_split);
-        p.n_field_tasks = (n - p.n_tri + F - 1) / F;
+        p.n_fblocks = (n - p.n_tri + F - 1) / F;
+        p.n_fslots = p.n_fblocks > 0 ? (p.n_rows + symba::kFieldSegRows - 1) / symba::kFieldSegRows : 0;
+        p.n_field_tasks = p.n_fblocks * p.n_fslots;
     }
     p.n_blk = (n + symba::kFinBodies - 1) / symba::kFinBodies;
-    p.partial_doubles = (size_t)p.n_slots * 3 * (size_t)p.n_tri;
+    p.partial_doubles = (size_t)p.n_slots * 3 * (size_t)p.n_tri + (size_t)p.n_fslots * 3 * (size_t)(n - p.n_tri);
     return p;
 }
 
@@ -305,6 +308,7 @@ void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int
     d.B = p.B; d.n_split = p.n_split; d.n_whole = p.n_whole; d.n_slots = p.n_slots;
     d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
     d.n_blk = p.n_blk; d.field_block = (int64_t)field_rows * symba::kWave;
+    d.n_fslots = p.n_fslots;
     (void)n_m;
 }
 
@@ -489,6 +493,7 @@ int evaluate(symba_ctx *c, const symba_state *s, int64_t n, int64_t n_m, double 
     fill_desc(d, *s, *out, n, n_m, dt, rcrit_factor, p, field_rows);
     d.task_base = 0;
     d.partial = c->partial;
+    d.fpartial = d.partial + d.n_slots * 3 * d.n_tri;
     d.parent = c->parent;
     d.touched = c->touched;
     d.blk_groups = c->blk_groups;
@@ -813,6 +818,7 @@ int batch_impl(symba_ctx *c, const symba_problem *probs, int32_t n_problems, voi
         }
         d.task_base = task_total;
         d.partial = c->partial + partial_off;
+        d.fpartial = d.partial + d.n_slots * 3 * d.n_tri;
         d.parent = c->parent + body_off;
         d.touched = c->touched + body_off;
         d.blk_groups = c->blk_groups + blk_off;
@@ -965,8 +971,8 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
             tasks[3 * f + 2] = T.J * rows + T.q;
         } else {
             tasks[3 * f] = 1;
-            tasks[3 * f + 1] = t - p.n_tri_tasks;
-            tasks[3 * f + 2] = 0;
+            tasks[3 * f + 1] = (t - p.n_tri_tasks) / p.n_fslots;
+            tasks[3 * f + 2] = (t - p.n_tri_tasks) % p.n_fslots;
         }
     }
     return total;

@@ -11,6 +11,7 @@ constexpr int kFinalizeThreads = 256;
 constexpr int kFinBodies = 32;     // bodies per finalize block
 constexpr int kFinSplit = kFinalizeThreads / kFinBodies;  // threads per body in the slot sums
 constexpr int kMaxBuckets = 4096;  // index buckets of the canonical pair order
+constexpr int kFieldSegRows = 192; // massive rows per field task (its segment of the rows; 3 tiles of 64)
 constexpr int kBoxDoubles = 16;    // tile box record: pos lo[3] hi[3], vel lo[3] hi[3], qmax, pad
 constexpr int kGatherWaves = 4;    // tiles per block of the tile-box kernel
 constexpr int kBinTempInts = 2 * 2048 + 2 * 2048 + 2 * 2049;  // cell counts, fills, starts
@@ -68,6 +69,8 @@ struct Desc {
     int64_t field_block;  // field bodies per field task (64*field_rows)
     // scratch slices (context-owned)
     double *partial;      // [n_slots][3][n_tri] per-slot partial sums
+    double *fpartial;     // [n_fslots][3][n - n_tri] field bodies' partial sums, one slot per segment
+    int64_t n_fslots;     // segments of kFieldSegRows massive rows (0 without field tasks)
     int32_t *parent;      // [n] union-find forest as offsets to the parent (0 = root), zero between calls
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
     int32_t *blk_groups;  // [n_blk] encounter groups rooted in each final-kernel body block

@@ -74,9 +74,15 @@ struct __align__(16) TaskLds {
             double2 xy[RS][2 * kWave], zm[RS][2 * kWave], vxy[RS][2 * kWave], vzq[RS][2 * kWave];
             double2 sxy[RS * kWave], szm[RS * kWave], svxy[RS * kWave], svzq[RS * kWave];
         } tile;
+        // a field task's segment of massive rows (each row once: every lane
+        // reads the same row at a time)
+        struct {
+            double2 xy[kFieldSegRows], zm[kFieldSegRows], vxy[kFieldSegRows], vzq[kFieldSegRows];
+        } seg;
         double comb[2][kTaskWaves][RS][3][kWave];
     };
 };
+static_assert(sizeof(TaskLds<1>::seg) <= sizeof(TaskLds<1>::tile), "a field segment fits the smallest tile area");
 
 // Per-wave LDS ring of screen candidates (i, j).  After every step fewer than
 // 64 are outstanding and one step pushes at most 64 per stationary slot, so a
@@ -667,7 +673,7 @@ struct TaskInfo {
     int64_t I, J;             // blocks of the pair
     int64_t ib, jb;           // first stationary and first streamed body
     int64_t slot_i, slot_j;   // split: partial slots of the stationary and the streamed side
-    int64_t fb;               // field: field block
+    int64_t fb, sg;           // field: field block and segment of massive rows
 };
 
 constexpr int kTaskWhole = 0, kTaskSplit = 1, kTaskField = 2;
@@ -676,7 +682,7 @@ template <int R>
 __device__ __forceinline__ TaskInfo decode_task(const Desc &d, int64_t lt) {
     TaskInfo T;
     T.r = T.q = 0;
-    T.I = T.J = T.ib = T.jb = T.slot_i = T.slot_j = T.fb = 0;
+    T.I = T.J = T.ib = T.jb = T.slot_i = T.slot_j = T.fb = T.sg = 0;
     if (lt < d.n_whole) {
         T.kind = kTaskWhole;
         whole_decode(d.B, d.n_split, lt, T.I, T.J);
@@ -698,7 +704,8 @@ __device__ __forceinline__ TaskInfo decode_task(const Desc &d, int64_t lt) {
     } else {
         T.kind = kTaskField;
         T.nq = T.nstat = 0;
-        T.fb = lt - d.n_tri_tasks;
+        T.fb = (lt - d.n_tri_tasks) / d.n_fslots;
+        T.sg = (lt - d.n_tri_tasks) % d.n_fslots;
     }
     return T;
 }
@@ -825,19 +832,28 @@ __device__ __forceinline__ void split_pair(const Desc &d, TaskLds<RS> &L, Queue 
     write_sums<R, RS, 1>(d, L, S, aj, t0, false, T.slot_i, T.ib, T.slot_j, T.jb);
 }
 
-// This wave's 16 rows [t0, t0 + 16) of staged massive tile q against the
-// lane's field bodies (one-sided pairs); returns the bit mask of the steps
-// whose screen passed somewhere in the wave.
+// Rows [u0, u1) (at most 16) of the staged segment (segment row u is massive
+// row s0 + u) against the lane's field bodies (one-sided pairs); returns the
+// bit mask (bit u - u0) of the rows whose screen passed somewhere in the wave.
 template <int RF, int RS, bool SCR, bool F32>
-__device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS> &L, int q, int64_t s0, int t0,
-                                                const Body (&fbody)[RF], double (&ax)[RF], double (&ay)[RF],
-                                                double (&az)[RF]) {
+__device__ __forceinline__ unsigned segment_rows(const Desc &d, const TaskLds<RS> &L, int u0, int u1,
+                                                 const Body (&fbody)[RF], double (&ax)[RF], double (&ay)[RF],
+                                                 double (&az)[RF]) {
     unsigned pending = 0;
-    for (int u = 0; u < kSteps; ++u) {
-        const int64_t row = s0 + q * kWave + t0 + u;
-        if (row >= d.n_rows) break;
+    for (int u = u0; u < u1; ++u) {
         // the same massive body in every lane
-        const Body I = SCR ? tile_body<RS, F32>(L, q, t0 + u) : tile_pos(L, q, t0 + u);
+        const double2 pxy = L.seg.xy[u], pzm = L.seg.zm[u];
+        Body I{pxy.x, pxy.y, pzm.x, pzm.y, 0.0, 0.0, 0.0, 0.0};
+        if (SCR) {
+            const double2 v = L.seg.vxy[u];
+            I.vx = v.x;
+            I.vy = v.y;
+            if constexpr (!F32) {
+                const double2 q = L.seg.vzq[u];
+                I.vz = q.x;
+                I.Q = q.y;
+            }
+        }
         unsigned long long any = 0;
 #pragma unroll
         for (int r = 0; r < RF; ++r) {
@@ -851,20 +867,24 @@ __device__ __forceinline__ unsigned field_range(const Desc &d, const TaskLds<RS>
             if (SCR)
                 any |= __builtin_amdgcn_ballot_w64(screen_pair<F32>(r2, Fb, I));
         }
-        if (SCR) pending |= nonzero(any) << u;
+        if (SCR) pending |= nonzero(any) << (u - u0);
     }
     return pending;
 }
 
-// Field block fb against every massive row, by the four waves of the
-// workgroup (wave w takes steps [16 w, 16 w + 16) of every 64 rows): one-sided
-// pairs; the field accelerations are complete at the end and written directly.
-
+// Field task: field block fb (RF tiles of 64 field bodies, RF per lane,
+// the same in all four waves) against segment sg of the massive rows
+// (kFieldSegRows rows from sg kFieldSegRows), staged once; wave w takes a
+// contiguous quarter of the segment.  The waves' sums are combined in a
+// fixed order and written to the field bodies' partial slot sg; the final
+// kernel adds the segments' slots in order.
 template <int RF, int RS, bool BIN, bool F32>
-__device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb) {
+__device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue &Q, int64_t fb, int64_t sg) {
     const int l = lane(), w = wave_id();
-    const int t0 = w * kSteps;
     const int64_t f0 = d.n_tri + fb * RF * kWave;
+    const int64_t s0 = sg * kFieldSegRows;
+    const int64_t left = d.n_rows - s0;
+    const int nrows = left < kFieldSegRows ? (int)left : kFieldSegRows;
     Body fbody[RF];
     double ax[RF], ay[RF], az[RF];
 #pragma unroll
@@ -872,47 +892,60 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         fbody[r] = load_body<true, F32>(d, f0 + r * kWave + l, d.n);
         ax[r] = ay[r] = az[r] = 0.0;
     }
-    for (int64_t s0 = 0; s0 < d.n_rows; s0 += RS * kWave) {
-        const int64_t left = d.n_rows - s0;
-        const int nq = left >= RS * kWave ? RS : (int)((left + kWave - 1) / kWave);
-        // lane q RF + r decides field tile r against massive tile q of the chunk
-        unsigned free_q = 0;
-        if (BIN) {
-            const bool apart = l >= nq * RF ||
-                               tiles_apart(d, field_box(d, fb * RF + l % RF), tri_box(d, s0 / kWave + l / RF));
-            const unsigned long long m = __ballot(apart);
-            for (int q = 0; q < nq; ++q) {
-                bool all = true;
-#pragma unroll
-                for (int r = 0; r < RF; ++r) all = all && ((m >> (q * RF + r)) & 1ull);
-                free_q |= (all ? 1u : 0u) << q;
-            }
-        }
-        stage<RS, F32>(d, L, s0, nq, d.n_rows);
-        __syncthreads();
+    // lane q RF + r decides field tile r against the segment's massive tile q
+    // (a segment is a whole number of 64-row tiles)
+    unsigned free_q = 0;
+    if (BIN) {
+        const int nq = (nrows + kWave - 1) / kWave;
+        const bool apart = l >= nq * RF ||
+                           tiles_apart(d, field_box(d, fb * RF + l % RF), tri_box(d, s0 / kWave + l / RF));
+        const unsigned long long m = __ballot(apart);
         for (int q = 0; q < nq; ++q) {
-            const bool apart = BIN && ((free_q >> q) & 1u);
-            unsigned pending = apart ? field_range<RF, RS, !BIN, F32>(d, L, q, s0, t0, fbody, ax, ay, az)
-                                     : field_range<RF, RS, true, F32>(d, L, q, s0, t0, fbody, ax, ay, az);
-            while (pending) {
-                const int u = __builtin_ctz(pending);
-                pending &= pending - 1;
-                const int64_t row = s0 + q * kWave + t0 + u;
-                const Body I = tile_body<RS, F32>(L, q, t0 + u);
+            bool all = true;
 #pragma unroll
-                for (int r = 0; r < RF; ++r) {
-                    const Body &Fb = fbody[r];
-                    const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
-                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
-                    const bool c = screen_pair<F32>(r2, Fb, I);
-                    const unsigned long long mask = __ballot(c);
-                    if (mask) push(Q, mask, c, row, f0 + r * kWave + l);
-                }
-                maybe_drain(d, Q);
-            }
+            for (int r = 0; r < RF; ++r) all = all && ((m >> (q * RF + r)) & 1ull);
+            free_q |= (all ? 1u : 0u) << q;
         }
-        __syncthreads();  // the tiles are restaged next round
     }
+    for (int e = (int)threadIdx.x; e < nrows; e += kTaskThreads) {
+        const Body b = load_body<false, F32>(d, s0 + e, d.n_rows);
+        L.seg.xy[e] = make_double2(b.x, b.y);
+        L.seg.zm[e] = make_double2(b.z, b.m);
+        L.seg.vxy[e] = make_double2(b.vx, b.vy);
+        L.seg.vzq[e] = make_double2(b.vz, b.Q);
+    }
+    __syncthreads();
+    constexpr int kQuarter = kFieldSegRows / kTaskWaves;
+    static_assert(kQuarter % kSteps == 0 && kWave % kSteps == 0, "a wave's rows split into whole 16-row runs");
+    const int r0 = w * kQuarter, r1 = min(r0 + kQuarter, nrows);
+    for (int u0 = r0; u0 < r1; u0 += kSteps) {
+        const int u1 = min(u0 + kSteps, r1);
+        const bool apart = BIN && ((free_q >> (u0 / kWave)) & 1u);
+        unsigned pending = apart ? segment_rows<RF, RS, !BIN, F32>(d, L, u0, u1, fbody, ax, ay, az)
+                                 : segment_rows<RF, RS, true, F32>(d, L, u0, u1, fbody, ax, ay, az);
+        while (pending) {
+            const int u = u0 + __builtin_ctz(pending);
+            pending &= pending - 1;
+            const double2 pxy = L.seg.xy[u], pzm = L.seg.zm[u], v = L.seg.vxy[u];
+            Body I{pxy.x, pxy.y, pzm.x, pzm.y, v.x, v.y, 0.0, 0.0};
+            if constexpr (!F32) {
+                const double2 q = L.seg.vzq[u];
+                I.vz = q.x;
+                I.Q = q.y;
+            }
+#pragma unroll
+            for (int r = 0; r < RF; ++r) {
+                const Body &Fb = fbody[r];
+                const double dx = Fb.x - I.x, dy = Fb.y - I.y, dz = Fb.z - I.z;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+                const bool c = screen_pair<F32>(r2, Fb, I);
+                const unsigned long long mask = __ballot(c);
+                if (mask) push(Q, mask, c, s0 + u, f0 + r * kWave + l);
+            }
+            maybe_drain(d, Q);
+        }
+    }
+    __syncthreads();  // every wave is done with the rows (the sums reuse their LDS)
 #pragma unroll
     for (int r = 0; r < RF; ++r) {
         L.comb[0][w][r][0][l] = ax[r];
@@ -920,21 +953,17 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         L.comb[0][w][r][2][l] = az[r];
     }
     __syncthreads();
+    const int64_t n_field = d.n - d.n_tri;
     for (int e = (int)threadIdx.x; e < RF * kWave; e += kTaskThreads) {
         const int r = e / kWave, ll = e % kWave;
-        const int64_t pos = f0 + e;
-        if (pos >= d.n) continue;
-        const int64_t k = d.bidx ? d.bidx[pos] : pos;
-        double sum[3];
+        const int64_t fpos = f0 + e - d.n_tri;
+        if (fpos >= n_field) continue;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double v = 0.0;
             for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[0][ww][r][c][ll];
-            sum[c] = v;
+            d.fpartial[(3 * sg + c) * n_field + fpos] = v;
         }
-        d.ax[k] = sum[0];
-        d.ay[k] = sum[1];
-        d.az[k] = sum[2];
     }
 }
 
@@ -983,7 +1012,7 @@ __device__ __forceinline__ void tile_task_once(const Desc &desc, int64_t t) {
     const Desc d = tile_view<BIN>(desc);
     const TaskInfo T = decode_task<R>(d, t - d.task_base);
     if (T.kind == kTaskField) {
-        field_task<RF, RS, BIN, F32>(d, L, Q, T.fb);
+        field_task<RF, RS, BIN, F32>(d, L, Q, T.fb, T.sg);
     } else {
         Raw raw[PF];
         load_task_bodies(d, T, raw);
@@ -1424,7 +1453,8 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     auto &part = F.part;
     const int col = tid % kFinBodies, split = tid / kFinBodies;
     const int64_t pos = lb * kFinBodies + col;  // position in the binned order
-    const bool own_sum = pos < d.n && (pos < d.n_tri || d.n_rows == 0);
+    const bool own_sum = pos < d.n;
+    const bool tri = pos < d.n_tri;  // massive: the triangle's slots; field: the segments' slots
     // the label's first loads are issued before the partial sums so that
     // their round trip overlaps them
     int64_t k = pos;
@@ -1436,15 +1466,17 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     }
     double sx = 0.0, sy = 0.0, sz = 0.0;
     if (own_sum) {
-        const int64_t per = (d.n_slots + kFinSplit - 1) / kFinSplit;
+        const int64_t slots = tri ? d.n_slots : d.n_fslots;
+        const int64_t stride = tri ? d.n_tri : d.n - d.n_tri;
+        const int64_t per = (slots + kFinSplit - 1) / kFinSplit;
         const int64_t c0 = split * per;
-        const int64_t c1 = (c0 + per) < d.n_slots ? (c0 + per) : d.n_slots;
-        const double *p = d.partial + pos;
+        const int64_t c1 = (c0 + per) < slots ? (c0 + per) : slots;
+        const double *p = tri ? d.partial + pos : d.fpartial + (pos - d.n_tri);
 #pragma unroll 8
         for (int64_t c = c0; c < c1; ++c) {
-            sx += p[(3 * c) * d.n_tri];
-            sy += p[(3 * c + 1) * d.n_tri];
-            sz += p[(3 * c + 2) * d.n_tri];
+            sx += p[(3 * c) * stride];
+            sy += p[(3 * c + 1) * stride];
+            sz += p[(3 * c + 2) * stride];
         }
     }
     part[split][0][col] = sx;
@@ -1453,16 +1485,10 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
     __syncthreads();
     bool nonfinite = false, root_of_group = false;
     if (split == 0 && pos < d.n) {
-        if (own_sum) {
-            for (int s2 = 1; s2 < kFinSplit; ++s2) {
-                sx += part[s2][0][col];
-                sy += part[s2][1][col];
-                sz += part[s2][2][col];
-            }
-        } else {  // a field body's sums, written by its field task
-            sx = d.ax[k];
-            sy = d.ay[k];
-            sz = d.az[k];
+        for (int s2 = 1; s2 < kFinSplit; ++s2) {
+            sx += part[s2][0][col];
+            sy += part[s2][1][col];
+            sz += part[s2][2][col];
         }
         if (d.ind) {  // the Sun's pull and the indirect term
             const double px = d.x[k], py = d.y[k], pz = d.z[k];
@@ -1472,11 +1498,9 @@ __device__ __forceinline__ void sum_and_label(FinLds &F, const Desc &d, int64_t 
             sy = sy - q * py - a0y;
             sz = sz - q * pz - a0z;
         }
-        if (own_sum || d.ind) {
-            d.ax[k] = sx;
-            d.ay[k] = sy;
-            d.az[k] = sz;
-        }
+        d.ax[k] = sx;
+        d.ay[k] = sy;
+        d.az[k] = sz;
         if (d.kvx) {  // the step's closing half kick
             d.kvx[k] = __builtin_fma(d.kick_h, sx, d.kvx[k]);
             d.kvy[k] = __builtin_fma(d.kick_h, sy, d.kvy[k]);

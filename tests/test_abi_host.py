@@ -84,9 +84,10 @@ def expand(tasks, n, n_m, rows, field_rows):
                 I, J = I[keep], J[keep]
             lo, hi = np.minimum(I, J), np.maximum(I, J)
             keys.append(lo * n + hi)
-        else:
+        else:  # field block a against segment b of the massive rows
             f = np.arange(n_tri + a * F, min(n_tri + a * F + F, n))
-            I, J = np.meshgrid(np.arange(n_rows), f, indexing="ij")
+            rows_seg = np.arange(b * B.FIELD_SEG_ROWS, min((b + 1) * B.FIELD_SEG_ROWS, n_rows))
+            I, J = np.meshgrid(rows_seg, f, indexing="ij")
             keys.append(I.ravel() * n + J.ravel())
     return np.sort(np.concatenate(keys)) if keys else np.zeros(0, np.int64)
 
@@ -99,7 +100,7 @@ def trapezoid(n, n_m):
 
 @pytest.mark.parametrize("n,n_m", [(1, 0), (1, 1), (2, 1), (2, 2), (5, 0), (64, 63), (65, 64), (130, 130),
                                    (300, 299), (257, 256), (700, 699), (400, 90), (333, 1), (200, 64),
-                                   (1000, 999), (900, 128)])
+                                   (1000, 999), (900, 128), (1200, 500), (700, 385)])
 @pytest.mark.parametrize("rows,field_rows", [(1, 1), (2, 1), (4, 2)])
 def test_plan_covers_trapezoid_once(n, n_m, rows, field_rows):
     tasks = B.plan_tasks(n, n_m, rows, field_rows)
