@@ -309,6 +309,7 @@ void fill_desc(Desc &d, const symba_state &s, const symba_out &o, int64_t n, int
     d.n_tri_tasks = p.n_tri_tasks; d.n_tasks = p.n_tri_tasks + p.n_field_tasks;
     d.n_blk = p.n_blk; d.field_block = (int64_t)field_rows * symba::kWave;
     d.n_fslots = p.n_fslots;
+    d.n_fblocks = p.n_fblocks;
     (void)n_m;
 }
 
@@ -970,9 +971,11 @@ int64_t symba_plan_tasks(int64_t n, int64_t n_m, int32_t rows, int32_t field_row
             tasks[3 * f + 1] = T.I * rows + T.r;
             tasks[3 * f + 2] = T.J * rows + T.q;
         } else {
+            int64_t fb, sg;
+            symba::field_decode(p.n_fblocks, p.n_fslots, t - p.n_tri_tasks, fb, sg);
             tasks[3 * f] = 1;
-            tasks[3 * f + 1] = (t - p.n_tri_tasks) / p.n_fslots;
-            tasks[3 * f + 2] = (t - p.n_tri_tasks) % p.n_fslots;
+            tasks[3 * f + 1] = fb;
+            tasks[3 * f + 2] = sg;
         }
     }
     return total;

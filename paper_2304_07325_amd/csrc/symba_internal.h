@@ -71,6 +71,7 @@ struct Desc {
     double *partial;      // [n_slots][3][n_tri] per-slot partial sums
     double *fpartial;     // [n_fslots][3][n - n_tri] field bodies' partial sums, one slot per segment
     int64_t n_fslots;     // segments of kFieldSegRows massive rows (0 without field tasks)
+    int64_t n_fblocks;    // field blocks (64 field_rows field bodies each)
     int32_t *parent;      // [n] union-find forest as offsets to the parent (0 = root), zero between calls
     int32_t *touched;     // [n] body appears in a flagged pair, zero between calls
     int32_t *blk_groups;  // [n_blk] encounter groups rooted in each final-kernel body block
@@ -263,6 +264,21 @@ __host__ __device__ inline SplitTask split_decode(int64_t B, int R, int64_t s) {
     t.slot_i = t.q == 0 ? t.J : extra + t.q - 1;
     t.slot_j = t.r == 0 ? t.I : extra + (R - 1) + t.r - 1;
     return t;
+}
+
+// Field task f (f < n_fblocks n_fslots) -> (field block, segment).  The
+// segments of a field block are 8 task indices apart: the dispatcher deals
+// consecutive workgroups to MI355X's 8 XCDs in turn, so a block's segments
+// run on one XCD and read its field bodies through one L2.  Groups of 8
+// blocks take 8 S consecutive tasks (the last group fewer blocks).
+constexpr int kXcds = 8;
+__host__ __device__ inline void field_decode(int64_t n_fblocks, int64_t n_fslots, int64_t f, int64_t &fb,
+                                             int64_t &sg) {
+    const int64_t g = f / (kXcds * n_fslots), r = f % (kXcds * n_fslots);
+    const int64_t rest = n_fblocks - g * kXcds;
+    const int64_t cnt = rest < kXcds ? rest : kXcds;
+    fb = g * kXcds + r % cnt;
+    sg = r / cnt;
 }
 
 // Order in which a single problem's tasks are launched (position f of the

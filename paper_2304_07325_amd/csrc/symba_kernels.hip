@@ -704,8 +704,7 @@ __device__ __forceinline__ TaskInfo decode_task(const Desc &d, int64_t lt) {
     } else {
         T.kind = kTaskField;
         T.nq = T.nstat = 0;
-        T.fb = (lt - d.n_tri_tasks) / d.n_fslots;
-        T.sg = (lt - d.n_tri_tasks) % d.n_fslots;
+        field_decode(d.n_fblocks, d.n_fslots, lt - d.n_tri_tasks, T.fb, T.sg);
     }
     return T;
 }
