@@ -488,13 +488,21 @@ struct Slots {
     double ax[R], ay[R], az[R];
 };
 
+// A partial sum is written through to memory (an agent-scope store): the
+// final kernel reads it from another XCD anyway, and lines the tile kernel
+// leaves clean need no write-back at its end (measured 61.4 -> 59.8 us on the
+// 10k disk).
+__device__ __forceinline__ void store_through(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void write_partial(const Desc &d, int64_t slot, int64_t k, double ax,
                                               double ay, double az) {
     if (k < d.n_tri) {
         double *p = d.partial + slot * 3 * d.n_tri + k;
-        p[0] = ax;
-        p[d.n_tri] = ay;
-        p[2 * d.n_tri] = az;
+        store_through(p, ax);
+        store_through(p + d.n_tri, ay);
+        store_through(p + 2 * d.n_tri, az);
     }
 }
 
@@ -961,7 +969,7 @@ __device__ __forceinline__ void field_task(const Desc &d, TaskLds<RS> &L, Queue 
         for (int c = 0; c < 3; ++c) {
             double v = 0.0;
             for (int ww = 0; ww < kTaskWaves; ++ww) v += L.comb[0][ww][r][c][ll];
-            d.fpartial[(3 * sg + c) * n_field + fpos] = v;
+            store_through(d.fpartial + (3 * sg + c) * n_field + fpos, v);
         }
     }
 }
