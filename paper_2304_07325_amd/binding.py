@@ -322,17 +322,46 @@ class Context:
 
     def kick_encounter_batch(self, problems, stream=None):
         """problems: list of (state, n_m, dt, rcrit_factor, Outputs)."""
-        arr = (symba_problem * len(problems))()
-        for k, (state, n_m, dt, f, out) in enumerate(problems):
-            arr[k].state = _state_struct(state, out)
-            arr[k].n = int(state["x"].numel())
-            arr[k].n_m = int(n_m)
-            arr[k].dt = float(dt)
-            arr[k].rcrit_factor = float(f)
-            arr[k].out = out.c_struct()
-        rc = lib().symba_kick_encounter_batch(self._h, arr, len(problems), _stream_handle(stream))
-        _check(rc, "symba_kick_encounter_batch")
+        arr = (symba_problem * len(problems))(*(problem_struct(*p) for p in problems))
+        self.kick_encounter_batch_structs(arr, stream)
         return [p[4] for p in problems]
+
+    def kick_encounter_batch_structs(self, arr, stream=None):
+        """symba_kick_encounter_batch on a ctypes array of symba_problem built by
+        problem_struct (for callers that keep the structs of resident problems)."""
+        rc = lib().symba_kick_encounter_batch(self._h, arr, len(arr), _stream_handle(stream))
+        _check(rc, "symba_kick_encounter_batch")
+
+    def step_batch_structs(self, arr, stream=None):
+        """symba_step_batch on a ctypes array of symba_step_problem built by
+        step_problem_struct."""
+        _check(lib().symba_step_batch(self._h, arr, len(arr), _stream_handle(stream)), "symba_step_batch")
+
+
+def problem_struct(state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs) -> symba_problem:
+    """The symba_problem of one batch entry (pointers into state and out, which
+    must outlive every call that uses it)."""
+    p = symba_problem()
+    p.state = _state_struct(state, out)
+    p.n = int(state["x"].numel())
+    p.n_m = int(n_m)
+    p.dt = float(dt)
+    p.rcrit_factor = float(rcrit_factor)
+    p.out = out.c_struct()
+    return p
+
+
+def step_problem_struct(state: dict, n_m: int, h: float, rcrit_factor: float, out: Outputs) -> symba_step_problem:
+    """The symba_step_problem of one step-batch entry (pointers as problem_struct)."""
+    p = symba_step_problem()
+    _state_struct(state, out)
+    p.state = symba_mstate(*(state[key].data_ptr() for key in STATE_KEYS))
+    p.n = int(state["x"].numel())
+    p.n_m = int(n_m)
+    p.h = float(h)
+    p.rcrit_factor = float(rcrit_factor)
+    p.out = out.c_struct()
+    return p
 
 
 def kick_encounter_noalloc(state: dict, n_m: int, dt: float, rcrit_factor: float, out: Outputs,

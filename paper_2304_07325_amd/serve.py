@@ -56,6 +56,7 @@ class _Sim:
     dev: dict | None = None
     out: object | None = None
     acc: np.ndarray | None = None   # step mode: accelerations at `state`, kept while evicted
+    cprob: object | None = None     # the library's problem struct while resident (pointers into dev and out)
 
     @property
     def resident_bytes(self) -> int:
@@ -94,6 +95,9 @@ class GpuIO:
                                                    stream=st)
                 else:
                     s.out.acc.copy_(self.torch.from_numpy(s.acc))
+                s.cprob = self.B.step_problem_struct(s.dev, s.n_m, self.server.dt, self.server.f, s.out)
+            else:
+                s.cprob = self.B.problem_struct(s.dev, s.n_m, self.server.dt, self.server.f, s.out)
 
     def evict(self, s: _Sim, stream=None):
         """Drop simulation s from the device (in step mode keeping its advanced
@@ -105,18 +109,19 @@ class GpuIO:
                 s.acc = s.out.acc.cpu().numpy()
         s.dev = None
         s.out = None
+        s.cprob = None
 
     def issue(self, lane: int, sims, stream=None):
         """Enqueue one batched call on `lane` (or on `stream`); returns the event
         recorded after it."""
         st = stream if stream is not None else self.streams[lane]
-        srv = self.server
-        probs = [(s.dev, s.n_m, srv.dt, srv.f, s.out) for s in sims]
+        step = self.server.mode == "step"
+        arr = ((self.B.symba_step_problem if step else self.B.symba_problem) * len(sims))(*(s.cprob for s in sims))
         with self._stream_ctx(st):
-            if srv.mode == "step":
-                self.ctxs[lane].step_batch(probs, stream=st)
+            if step:
+                self.ctxs[lane].step_batch_structs(arr, stream=st)
             else:
-                self.ctxs[lane].kick_encounter_batch(probs, stream=st)
+                self.ctxs[lane].kick_encounter_batch_structs(arr, stream=st)
             ev = self.torch.cuda.Event()
             ev.record(st if st is not None else self.torch.cuda.current_stream())
         return ev
