@@ -259,8 +259,15 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         nb += __popcll(mask);
     }
     __syncthreads();
-    if (nb > kEncGroupBodies) {
+    if (nb > kEncGroupBodies) {  // report it, and unmark the bodies the table marked
         if (l == 0) e.ctl[kEncCtlSkipped] = 1;
+        if (full)
+            for (int t = l; t < np; t += kGroupThreads) {
+                const int p = e.gp[p0 + t];
+                e.ingroup[e.pair_i[p]] = 0;
+                e.ingroup[e.pair_j[p]] = 0;
+            }
+        __syncthreads();
         return false;
     }
     for (int t = l; t < np; t += kGroupThreads) {
