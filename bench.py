@@ -145,6 +145,18 @@ def cpu_baseline(disk, n_m, dt, f, budget_s=15.0):
         if time.perf_counter() - t0 >= budget_s / 3 or done_p >= 100:
             break
     el_p = time.perf_counter() - t0
+    # the encounter step's oracle (numpy, one thread) on the paper's 100-body
+    # accuracy disk, for the GPU's steps/s on the same disk
+    from oracle import symba_enc
+    acc_disk = dg.make_accuracy_disk(n=100)
+    s_e, h_e = acc_disk.state(0), acc_disk.dt
+    acc_e, pairs_e = symba_enc.prepare(s_e, acc_disk.n_massive, h_e, f, ora=o)
+    done_e, flagged_e, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s / 5 and done_e < 20000:
+        s_e, acc_e, pairs_e = symba_enc.step(s_e, acc_disk.n_massive, h_e, f, acc_e, pairs_e, ora=o)
+        done_e += 1
+        flagged_e += len(pairs_e)
+    el_e = time.perf_counter() - t0
     info = cpu_info()
     return dict(value=pairs * done / el, unit="pair-interactions/s", cores=1, kind="oracle",
                 sample=f"{done} evaluations of the 10k disk (states 0..{done - 1}), single thread pinned to core "
@@ -153,7 +165,10 @@ def cpu_baseline(disk, n_m, dt, f, budget_s=15.0):
                 all_cores={"value": pairs * done_p / el_p, "unit": "pair-interactions/s", "threads": threads,
                            "sample": f"{done_p} evaluations of the 10k disk (states 0..{done_p - 1}), {el_p:.1f} s",
                            "kind": "oracle loop nest built with OpenMP: folded rows, thread-private "
-                                   "accumulators summed in thread order (context, not the parity reference)"})
+                                   "accumulators summed in thread order (context, not the parity reference)"},
+                encounter_step={"value": done_e / el_e, "unit": "steps/s", "kind": "oracle (encounter step, numpy)",
+                                "sample": f"the first {done_e} 0.1-year steps of the 100-body accuracy disk, "
+                                          f"{flagged_e} flagged pairs in all, {el_e:.1f} s"})
 
 
 def main():
