@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kTableThreads = 1024;
 constexpr int kGroupThreads = 64;         // one wave per group
-constexpr int kGroupBlocks = 1024;        // workgroups of a group launch (each takes groups g, g + 1024, ...)
+constexpr int kGroupBlocks = 1024;        // most workgroups of a group launch (each takes groups g, g + grid, ...)
 constexpr int kEnds = 2 * kEncGroupBodies;  // pair endpoints of a group, padded to a power of two
 constexpr int kStatusEncSkipped = 4;      // SYMBA_STATUS_ENC_SKIPPED
 constexpr int kStatusCapacityBit = 1;     // SYMBA_STATUS_CAPACITY
@@ -223,7 +223,11 @@ struct GroupLds {
 __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
     const int l = lane();
     const int p0 = e.gstart[g], np = e.gstart[g + 1] - p0;
-    for (int t = l; t < kEnds / 2; t += kGroupThreads) {
+    // the endpoints, padded to a power of two no larger than needed (every
+    // pass of the sort is a round of dependent LDS accesses and a barrier)
+    int ends = 2;
+    while (ends < 2 * np) ends <<= 1;
+    for (int t = l; t < ends / 2; t += kGroupThreads) {
         int a = INT_MAX, b = INT_MAX;
         if (t < np) {
             const int p = e.gp[p0 + t];
@@ -234,9 +238,9 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         G.ends[2 * t + 1] = b;
     }
     __syncthreads();
-    for (int k = 2; k <= kEnds; k <<= 1) {
+    for (int k = 2; k <= ends; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = l; i < kEnds; i += kGroupThreads) {
+            for (int i = l; i < ends; i += kGroupThreads) {
                 const int o = i ^ j;
                 if (o > i) {
                     const int a = G.ends[i], b = G.ends[o];
@@ -504,13 +508,21 @@ hipError_t launch_enc_table(const EncDesc &e, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// Workgroups of a group launch: a problem of n bodies has at most n / 2
+// groups, and the dispatcher hands out about 200 workgroups per microsecond,
+// so a small problem gets a small grid (the launch is mostly empty).
+static unsigned group_blocks(int64_t n) {
+    const int64_t b = n / 8;
+    return (unsigned)(b < 64 ? 64 : (b > kGroupBlocks ? kGroupBlocks : b));
+}
+
 hipError_t launch_enc_groups(const EncDesc &e, hipStream_t stream) {
-    hipLaunchKernelGGL(k_enc_groups, dim3(kGroupBlocks), dim3(kGroupThreads), 0, stream, e);
+    hipLaunchKernelGGL(k_enc_groups, dim3(group_blocks(e.n)), dim3(kGroupThreads), 0, stream, e);
     return hipGetLastError();
 }
 
 hipError_t launch_enc_level0(const EncDesc &e, hipStream_t stream) {
-    hipLaunchKernelGGL(k_enc_level0, dim3(kGroupBlocks), dim3(kGroupThreads), 0, stream, e);
+    hipLaunchKernelGGL(k_enc_level0, dim3(group_blocks(e.n)), dim3(kGroupThreads), 0, stream, e);
     return hipGetLastError();
 }
 
