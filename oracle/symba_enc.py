@@ -105,7 +105,10 @@ def force_factor(k, r, r0):
 def encounter(dx, dv, radius, tau):
     """The close-encounter test with radius `radius` over an interval tau:
     inside now, inside at the linearly extrapolated end, or a closest
-    approach within the interval that is inside."""
+    approach within the interval that is inside.  A negative tau (a step
+    backwards in time) tests the reversed motion over |tau|."""
+    if tau < 0.0:
+        dv, tau = -dv, -tau
     r2 = float(dx @ dx)
     v2 = float(dv @ dv)
     vr = float(dx @ dv)

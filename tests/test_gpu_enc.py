@@ -330,3 +330,19 @@ def test_binned_problem_groups(ora):
     G.say("binned 20k hot disk, 1 step,", len(pairs), "pairs")
     _compare_step(dev, ora, s, n, h, acc, pairs)
     dev.close()
+
+
+def test_flyby_backwards_step_by_step(ora):
+    """Negative steps (h < 0): the level tests run on the reversed motion on
+    both sides; the flyby integrated backwards from inside the critical
+    radius, through closest approach."""
+    x, v, m = _flyby(sep=0.15)
+    s = _state(x, v, m)
+    s = dict(s, vx=-s["vx"], vy=-s["vy"], vz=-s["vz"])   # run the flyby in reverse
+    h = -0.025
+    acc, pairs = E.prepare(s, 2, h, F, ora=ora)
+    dev = Dev(2)
+    G.say("flyby backwards, 12 steps")
+    for _ in range(12):
+        s, acc, pairs = _compare_step(dev, ora, s, 2, h, acc, pairs)
+    dev.close()

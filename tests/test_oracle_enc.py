@@ -318,3 +318,19 @@ def test_planted_mistakes_fail_a_pin(monkeypatch, mistake):
             gradient_ok = False
     err, de = _flyby_errors()
     assert not gradient_ok or err > 1e-6 or de > 1e-6, (mistake, err, de)
+
+
+def test_negative_substeps_test_the_reversed_motion():
+    """Over a negative interval the test looks backwards: a pair that
+    approaches (will meet within tau) has receded over -tau, and the test
+    over -tau of the motion equals the test over tau of the reversed motion."""
+    dx = np.array([1.0, 0.0, 0.0])
+    dv = np.array([-1.0, 0.0, 0.0])   # closing at unit speed
+    assert E.encounter(dx, dv, 0.5, 0.8)        # inside 0.5 within 0.8 ahead
+    assert not E.encounter(dx, dv, 0.5, -0.8)   # was farther apart before
+    assert E.encounter(dx, -dv, 0.5, -0.8)      # receding pair met in the past
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        a, w = rng.normal(size=3), rng.normal(size=3)
+        rad, tau = rng.uniform(0.1, 2.0), rng.uniform(0.01, 2.0)
+        assert E.encounter(a, w, rad, -tau) == E.encounter(a, -w, rad, tau)
