@@ -346,3 +346,30 @@ def test_flyby_backwards_step_by_step(ora):
     for _ in range(12):
         s, acc, pairs = _compare_step(dev, ora, s, 2, h, acc, pairs)
     dev.close()
+
+
+@pytest.mark.parametrize("n,n_m", [(1, 1), (2, 0), (3, 1), (70, 0)])
+def test_degenerate_problems_are_the_plain_step(n, n_m):
+    """One body, or no massive body, or one massive row: no pair can be
+    flagged and the encounter step is symba_step bit for bit."""
+    rng = np.random.default_rng(n)
+    a = rng.uniform(1.0, 3.0, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    x = np.c_[a * np.cos(th), a * np.sin(th), rng.normal(0, 0.01, n)]
+    v = np.c_[-np.sin(th), np.cos(th), np.zeros(n)] / np.sqrt(a)[:, None]
+    s = _state(x, v, np.full(n, 1e-9))
+    h = 0.05
+    plain, enc = Dev(n), Dev(n)
+    plain.load(s)
+    enc.load(s)
+    plain.ctx.kick_encounter(plain.st, n_m, abs(h), F, out=plain.out)
+    enc.ctx.enc_prepare(enc.st, n_m, h, F, enc.out)
+    for _ in range(3):
+        plain.ctx.step(plain.st, n_m, h, F, plain.out)
+        enc.ctx.step_enc(enc.st, n_m, h, F, enc.out)
+    a_, b_ = plain.state(), enc.state()
+    for k in KEYS:
+        assert a_[k].tobytes() == b_[k].tobytes(), k
+    assert enc.out.to_host()["status"] == 0
+    plain.close()
+    enc.close()
