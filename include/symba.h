@@ -79,6 +79,9 @@ extern "C" {
                                    as single tile pairs at the end of the tile kernel.  -1 = automatic
                                    (the autotuner's choice, else a rule by launch depth), 0..8 = that many
                                    (clamped to what the fold has) */
+#define SYMBA_OPT_ENC_FUSE 9    /* symba_step_enc / symba_enc_prepare on problems of at most 256 bodies:
+                                   1 (default) = the work around the evaluation in two fused launches,
+                                   0 = the general launches (the same results, bit for bit) */
 
 /* Values of SYMBA_OPT_ACC.  The paper's loop (Sec. 2) sums the pair
  * interactions, the kick term of the democratic heliocentric splitting

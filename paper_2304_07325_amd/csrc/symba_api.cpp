@@ -57,6 +57,7 @@ struct symba_ctx {
     // options
     int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0, opt_acc = 0;
     int opt_split = -1;  // split diagonals of the folded triangle, -1 = automatic
+    int opt_enc_fuse = 1;  // fused encounter-step launches for one-block problems
     double *ind = nullptr;  // [max_n / kIndBodies + max_problems][3] indirect-term partial sums (SYMBA_ACC_HELIO)
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
@@ -463,6 +464,10 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             if (value < -1 || value > kMaxSplit) return SYMBA_EINVAL;
             c->opt_split = value;
             return SYMBA_OK;
+        case SYMBA_OPT_ENC_FUSE:
+            if (value != 0 && value != 1) return SYMBA_EINVAL;
+            c->opt_enc_fuse = value;
+            return SYMBA_OK;
         case SYMBA_OPT_ACC:
             if (value != SYMBA_ACC_INTERACTION && value != SYMBA_ACC_HELIO) return SYMBA_EINVAL;
             c->opt_acc = value;
@@ -689,10 +694,14 @@ bool bad_mstate(const symba_mstate *s) {
     return !s || !s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m || !s->rh;
 }
 
+// Problems of one drift block take the fused encounter launches.
+bool enc_fused(const symba_ctx *c, int64_t n) { return c->opt_enc_fuse && symba::step_blocks(n) == 1; }
+
 // Level-0 reweighting of the evaluation in `out` (pairs, groups and
 // Newtonian accelerations at s), then the closing kick when e.kick_h != 0.
-int enc_finish(symba::EncDesc e, hipStream_t stream) {
+int enc_finish(const symba_ctx *c, symba::EncDesc e, hipStream_t stream) {
     e.mark = 0;
+    if (enc_fused(c, e.n)) return symba::launch_enc_post_block(e, stream) == hipSuccess ? SYMBA_OK : SYMBA_EDEVICE;
     if (symba::launch_enc_table(e, stream) != hipSuccess || symba::launch_enc_level0(e, stream) != hipSuccess ||
         symba::launch_enc_kick(e, stream) != hipSuccess)
         return SYMBA_EDEVICE;
@@ -713,7 +722,7 @@ int symba_enc_prepare(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_
     if (rc != SYMBA_OK) return rc;
     symba::EncDesc e = enc_desc(c, s, n, n_m, h, rcrit_factor, out);
     e.kick_h = 0.0;
-    return enc_finish(e, (hipStream_t)stream);
+    return enc_finish(c, e, (hipStream_t)stream);
 }
 
 int symba_step_enc(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, double h, double rcrit_factor,
@@ -739,11 +748,13 @@ int symba_step_enc(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t n_m, 
     symba::EncDesc e = enc_desc(c, s, n, n_m, h, rcrit_factor, out);
     e.mark = 1;
     const hipStream_t st = (hipStream_t)stream;
-    if (symba::launch_drifts_enc(sd, e, st) != hipSuccess) return SYMBA_EDEVICE;
+    const hipError_t de = enc_fused(c, n) ? symba::launch_enc_drifts_block(sd, e, st)
+                                          : symba::launch_drifts_enc(sd, e, st);
+    if (de != hipSuccess) return SYMBA_EDEVICE;
     const symba_state cs{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m, s->rh};
     int rc = evaluate(c, &cs, n, n_m, std::fabs(h), rcrit_factor, out, stream, nullptr, 0.0, nullptr, true);
     if (rc != SYMBA_OK) return rc;
-    return enc_finish(e, st);
+    return enc_finish(c, e, st);
 }
 
 namespace {

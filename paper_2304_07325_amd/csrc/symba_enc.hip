@@ -20,6 +20,7 @@
 // level k + 1; kick for tau / 2.  Level L tests nothing and drifts its
 // bodies.  The recursion runs as a loop over (level, substep) with the
 // pairs' levels in LDS.
+#include "symba_drift.h"
 #include "symba_internal.h"
 #include "symba_kepler.h"
 
@@ -39,6 +40,14 @@ static_assert((kEnds & (kEnds - 1)) == 0, "the endpoint sort needs a power of tw
 static_assert((kEncMaxPairs & (kEncMaxPairs - 1)) == 0, "the table sort needs a power of two");
 
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// A group is worked on by one wave: its LDS is ordered among the wave's
+// lanes by a wave barrier (several waves of a block may run different groups).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // f_3 and its derivative at x clipped to [0, 1].
 __device__ __forceinline__ void partition(double x, double &f, double &df) {
@@ -109,9 +118,9 @@ __device__ __forceinline__ bool encounter(double dx, double dy, double dz, doubl
 // (group label, pair index), so each group's pairs are contiguous and in the
 // pairs' order and the groups are in the order of their labels.
 
-__global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
-    __shared__ unsigned long long key[kEncMaxPairs];
-    __shared__ int wave_sum[kTableThreads / kWave];
+template <int THREADS>
+__device__ void build_table(const EncDesc &e, unsigned long long *key) {
+    __shared__ int wave_sum[THREADS / kWave];
     const int tid = threadIdx.x;
     const int64_t np64 = *e.n_pairs;
     const int st = *e.status;
@@ -125,12 +134,12 @@ __global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
     const int np = (int)np64;
     int P2 = 1;
     while (P2 < np) P2 <<= 1;
-    for (int t = tid; t < P2; t += kTableThreads)
+    for (int t = tid; t < P2; t += THREADS)
         key[t] = t < np ? ((unsigned long long)(unsigned)e.group_id[e.pair_i[t]] << 32) | (unsigned)t : ~0ull;
     __syncthreads();
     for (int k = 2; k <= P2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < P2; i += kTableThreads) {
+            for (int i = tid; i < P2; i += THREADS) {
                 const int o = i ^ j;
                 if (o > i) {
                     const unsigned long long a = key[i], b = key[o];
@@ -143,9 +152,9 @@ __global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
             __syncthreads();
         }
     }
-    // group starts in this thread's chunk (at most 8 entries), then their
+    // group starts in this thread's chunk (at most 32 entries), then their
     // exclusive prefix over the threads
-    const int chunk = (np + kTableThreads - 1) / kTableThreads;
+    const int chunk = (np + THREADS - 1) / THREADS;
     const int c0 = tid * chunk, c1 = min(c0 + chunk, np);
     unsigned starts = 0;
     int count = 0;
@@ -163,7 +172,7 @@ __global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
     if (lane() == kWave - 1) wave_sum[tid / kWave] = incl;
     __syncthreads();
     int base = 0, total = 0;
-    for (int w = 0; w < kTableThreads / kWave; ++w) {
+    for (int w = 0; w < THREADS / kWave; ++w) {
         if (w < tid / kWave) base += wave_sum[w];
         total += wave_sum[w];
     }
@@ -184,14 +193,14 @@ __global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
     // groups over the limit are left out (and reported); the others' bodies
     // are marked for the drift kernels when asked
     int over = 0;
-    for (int gg = tid; gg < total; gg += kTableThreads) {
+    for (int gg = tid; gg < total; gg += THREADS) {
         const int big = (e.gstart[gg + 1] - e.gstart[gg]) > kEncGroupMaxPairs;
         e.gskip[gg] = big;
         over |= big;
     }
     if (__syncthreads_or(over) && tid == 0) e.ctl[kEncCtlSkipped] = 1;
     if (e.mark) {
-        for (int t = tid; t < np; t += kTableThreads) {
+        for (int t = tid; t < np; t += THREADS) {
             const int gg = (int)(key[t] >> 32);
             if (e.gstart[gg + 1] - e.gstart[gg] > kEncGroupMaxPairs) continue;
             const int p = (int)(key[t] & 0xffffffffull);
@@ -201,9 +210,14 @@ __global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
     }
 }
 
+__global__ __launch_bounds__(kTableThreads) void k_enc_table(const EncDesc e) {
+    __shared__ unsigned long long key[kEncMaxPairs];
+    build_table<kTableThreads>(e, key);
+}
+
 // ---------------------------------------------------------------------------
-// One group in a workgroup's LDS: its bodies (ascending global index) and its
-// pairs (the pairs' order) as local indices.
+// One group in LDS, worked on by one wave: its bodies (ascending global
+// index) and its pairs (the pairs' order) as local indices.
 
 struct GroupLds {
     double x[kEncGroupBodies], y[kEncGroupBodies], z[kEncGroupBodies];
@@ -237,7 +251,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         G.ends[2 * t] = a;
         G.ends[2 * t + 1] = b;
     }
-    __syncthreads();
+    wave_sync();
     for (int k = 2; k <= ends; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = l; i < ends; i += kGroupThreads) {
@@ -250,7 +264,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     }
     int nb = 0;
@@ -262,7 +276,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         if (first && pos < kEncGroupBodies) G.body[pos] = G.ends[t];
         nb += __popcll(mask);
     }
-    __syncthreads();
+    wave_sync();
     if (nb > kEncGroupBodies) {  // report it, and unmark the bodies the table marked
         if (l == 0) e.ctl[kEncCtlSkipped] = 1;
         if (full)
@@ -271,7 +285,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
                 e.ingroup[e.pair_i[p]] = 0;
                 e.ingroup[e.pair_j[p]] = 0;
             }
-        __syncthreads();
+        wave_sync();
         return false;
     }
     for (int t = l; t < np; t += kGroupThreads) {
@@ -309,7 +323,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         G.nb = nb;
         G.np = np;
     }
-    __syncthreads();
+    wave_sync();
     return true;
 }
 
@@ -346,7 +360,7 @@ __device__ void kick(GroupLds &G, int k, double dt) {
             G.vz[b] += dt * az;
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // The test of level k over tau on the level's pairs: flagged pairs go to
@@ -363,7 +377,7 @@ __device__ bool check(GroupLds &G, int k, double tau) {
         G.depth[t] = fl ? k + 1 : k;
         any = any || fl;
     }
-    return __syncthreads_or(any) != 0;
+    return __ballot(any) != 0;
 }
 
 // Kepler drift for tau of the bodies whose deepest pair is at level k
@@ -384,7 +398,7 @@ __device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
         G.vy[b] = vy;
         G.vz[b] = vz;
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // The group's drift over h: M substeps of level 1, each recursing as deep as
@@ -423,67 +437,73 @@ __device__ void integrate(GroupLds &G, double h) {
     }
 }
 
+// Level-0 reweighting of a group's accelerations: for each pair inside R_0,
+// m (F_0 - r F_0' - 1) (x_j - x_i) / r^3 on i and its opposite on j, summed
+// per body in the pairs' order and added to the Newtonian sums.  One wave.
+__device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
+    if (e.gskip[g] || !load_group(e, G, g, false)) return;
+    for (int b = lane(); b < G.nb; b += kGroupThreads) {
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        bool any = false;
+        for (int t = 0; t < G.np; ++t) {
+            const int i = G.pa[t], j = G.pb[t];
+            if (i != b && j != b) continue;
+            const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double r0 = G.rc[i] + G.rc[j];
+            if (r >= r0) continue;
+            any = true;
+            const double gf = (force_factor(0, r, r0) - 1.0) / (r * r * r);
+            if (b == i) {
+                const double s = G.m[j] * gf;
+                ax += s * dx;
+                ay += s * dy;
+                az += s * dz;
+            } else {
+                const double s = G.m[i] * gf;
+                ax -= s * dx;
+                ay -= s * dy;
+                az -= s * dz;
+            }
+        }
+        if (any) {
+            const int k = G.body[b];
+            e.ax[k] += ax;
+            e.ay[k] += ay;
+            e.az[k] += az;
+        }
+    }
+    wave_sync();
+}
+
+// One group's drift over the step, from its bodies in memory back to them
+// (the table marked them, so the drift kernels left them alone).  One wave.
+__device__ void drift_group(const EncDesc &e, GroupLds &G, int g) {
+    if (e.gskip[g] || !load_group(e, G, g, true)) return;
+    integrate(G, e.h);
+    for (int b = lane(); b < G.nb; b += kGroupThreads) {
+        const int k = G.body[b];
+        e.x[k] = G.x[b];
+        e.y[k] = G.y[b];
+        e.z[k] = G.z[b];
+        e.vx[k] = G.vx[b];
+        e.vy[k] = G.vy[b];
+        e.vz[k] = G.vz[b];
+        e.ingroup[k] = 0;
+    }
+    wave_sync();
+}
+
 __global__ __launch_bounds__(kGroupThreads) void k_enc_groups(const EncDesc e) {
     __shared__ GroupLds G;
     const int ng = e.ctl[kEncCtlGroups];
-    for (int g = blockIdx.x; g < ng; g += gridDim.x) {
-        if (e.gskip[g] || !load_group(e, G, g, true)) continue;
-        integrate(G, e.h);
-        for (int b = lane(); b < G.nb; b += kGroupThreads) {
-            const int k = G.body[b];
-            e.x[k] = G.x[b];
-            e.y[k] = G.y[b];
-            e.z[k] = G.z[b];
-            e.vx[k] = G.vx[b];
-            e.vy[k] = G.vy[b];
-            e.vz[k] = G.vz[b];
-            e.ingroup[k] = 0;
-        }
-        __syncthreads();
-    }
+    for (int g = blockIdx.x; g < ng; g += gridDim.x) drift_group(e, G, g);
 }
 
-// Level-0 reweighting of a group's accelerations: for each pair inside R_0,
-// m (F_0 - r F_0' - 1) (x_j - x_i) / r^3 on i and its opposite on j, summed
-// per body in the pairs' order and added to the Newtonian sums.
 __global__ __launch_bounds__(kGroupThreads) void k_enc_level0(const EncDesc e) {
     __shared__ GroupLds G;
     const int ng = e.ctl[kEncCtlGroups];
-    for (int g = blockIdx.x; g < ng; g += gridDim.x) {
-        if (e.gskip[g] || !load_group(e, G, g, false)) continue;
-        for (int b = lane(); b < G.nb; b += kGroupThreads) {
-            double ax = 0.0, ay = 0.0, az = 0.0;
-            bool any = false;
-            for (int t = 0; t < G.np; ++t) {
-                const int i = G.pa[t], j = G.pb[t];
-                if (i != b && j != b) continue;
-                const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
-                const double r0 = G.rc[i] + G.rc[j];
-                if (r >= r0) continue;
-                any = true;
-                const double gf = (force_factor(0, r, r0) - 1.0) / (r * r * r);
-                if (b == i) {
-                    const double s = G.m[j] * gf;
-                    ax += s * dx;
-                    ay += s * dy;
-                    az += s * dz;
-                } else {
-                    const double s = G.m[i] * gf;
-                    ax -= s * dx;
-                    ay -= s * dy;
-                    az -= s * dz;
-                }
-            }
-            if (any) {
-                const int k = G.body[b];
-                e.ax[k] += ax;
-                e.ay[k] += ay;
-                e.az[k] += az;
-            }
-        }
-        __syncthreads();
-    }
+    for (int g = blockIdx.x; g < ng; g += gridDim.x) level0_group(e, G, g);
 }
 
 // The closing kick v += kick_h a of every body (when kick_h is not 0), and
@@ -501,7 +521,76 @@ __global__ __launch_bounds__(256) void k_enc_kick(const EncDesc e) {
     }
 }
 
+// A problem of one block (n <= 256 bodies): the step's work before the
+// evaluation in one launch.  The first kick with the momentum's block sum,
+// the table (bodies of resolved groups marked), the Sun drift of every body
+// and the Kepler drift of the unmarked ones, the groups (wave w takes groups
+// w, w + 4, ...), then the momentum and the second Sun drift: the operations
+// of the separate launches in the same order, on the same values.
+constexpr int kFusedThreads = 256;
+constexpr int kFusedWaves = kFusedThreads / kWave;
+union FusedLds {
+    unsigned long long key[kEncMaxPairs];
+    GroupLds G[kFusedWaves];
+};
+
+__global__ __launch_bounds__(kFusedThreads) void k_enc_drifts_block(const StepDesc one, const EncDesc e) {
+    __shared__ FusedLds U;
+    double px, py, pz;
+    drift::kick_momentum(one, px, py, pz);
+    build_table<kFusedThreads>(e, U.key);
+    __syncthreads();  // the marks and the table are in place; the keys' LDS is free
+    drift::sun_kepler(one, px, py, pz);
+    __syncthreads();  // every body's Sun drift (and Kepler drift) is in memory
+    const int w = threadIdx.x / kWave;
+    const int ng = e.ctl[kEncCtlGroups];
+    for (int g = w; g < ng; g += kFusedWaves) drift_group(e, U.G[w], g);
+    __syncthreads();  // the groups' bodies are back in memory
+    const int64_t k = drift::body_of(one);
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (k < one.n) {
+        vx = one.vx[k];
+        vy = one.vy[k];
+        vz = one.vz[k];
+    }
+    drift::write_momentum(one, one.mom1, k, vx, vy, vz, px, py, pz);
+    drift::sun(one, px, py, pz);
+}
+
+// A problem of one block: the step's work after the evaluation in one
+// launch: the table of the new pairs, the level-0 reweighting (wave w takes
+// groups w, w + 4, ...), the closing kick and the status.
+__global__ __launch_bounds__(kFusedThreads) void k_enc_post_block(const EncDesc e) {
+    __shared__ FusedLds U;
+    build_table<kFusedThreads>(e, U.key);
+    __syncthreads();
+    const int w = threadIdx.x / kWave;
+    const int ng = e.ctl[kEncCtlGroups];
+    for (int g = w; g < ng; g += kFusedWaves) level0_group(e, U.G[w], g);
+    __syncthreads();
+    const int64_t k = threadIdx.x;
+    if (e.kick_h != 0.0 && k < e.n) {
+        e.vx[k] = __builtin_fma(e.kick_h, e.ax[k], e.vx[k]);
+        e.vy[k] = __builtin_fma(e.kick_h, e.ay[k], e.vy[k]);
+        e.vz[k] = __builtin_fma(e.kick_h, e.az[k], e.vz[k]);
+    }
+    if (k == 0 && e.ctl[kEncCtlSkipped]) {
+        *e.status |= kStatusEncSkipped;
+        e.ctl[kEncCtlSkipped] = 0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_enc_drifts_block(const StepDesc &one, const EncDesc &e, hipStream_t stream) {
+    hipLaunchKernelGGL(k_enc_drifts_block, dim3(1), dim3(kFusedThreads), 0, stream, one, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_post_block(const EncDesc &e, hipStream_t stream) {
+    hipLaunchKernelGGL(k_enc_post_block, dim3(1), dim3(kFusedThreads), 0, stream, e);
+    return hipGetLastError();
+}
 
 hipError_t launch_enc_table(const EncDesc &e, hipStream_t stream) {
     hipLaunchKernelGGL(k_enc_table, dim3(1), dim3(kTableThreads), 0, stream, e);

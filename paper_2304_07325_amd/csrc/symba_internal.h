@@ -164,6 +164,11 @@ hipError_t launch_enc_groups(const EncDesc &e, hipStream_t stream);
 hipError_t launch_enc_level0(const EncDesc &e, hipStream_t stream);
 hipError_t launch_enc_kick(const EncDesc &e, hipStream_t stream);
 hipError_t launch_drifts_enc(const StepDesc &one, const EncDesc &enc, hipStream_t stream);
+// The same for a problem of one block (n <= 256): everything before the
+// evaluation in one launch, and the table, reweighting and kick after it in
+// another.
+hipError_t launch_enc_drifts_block(const StepDesc &one, const EncDesc &enc, hipStream_t stream);
+hipError_t launch_enc_post_block(const EncDesc &e, hipStream_t stream);
 
 // Blocks of the drift kernels for n bodies, and their launch (first kick,
 // Sun drift, Kepler drift, Sun drift): one problem (`one`, list null) or the

@@ -373,3 +373,34 @@ def test_degenerate_problems_are_the_plain_step(n, n_m):
     assert enc.out.to_host()["status"] == 0
     plain.close()
     enc.close()
+
+
+@pytest.mark.parametrize("case", ["cluster", "flyby", "field"])
+def test_fused_small_problem_launches_are_bit_identical(case):
+    """Problems of one block run the encounter step in two fused launches;
+    the general launches (SYMBA_OPT_ENC_FUSE = 0) give the same bits."""
+    from paper_2304_07325_amd import binding as B
+    if case == "flyby":
+        x, v, m = _flyby(sep=0.15)
+        s, n_m, h = _state(x, v, m), 2, 0.025
+    else:
+        s, h = _cluster(), 0.01
+        n_m = 40 if case == "cluster" else 28
+    n = s["x"].size
+    fused, plain = Dev(n), Dev(n)
+    plain.ctx.set_option(B.OPT_ENC_FUSE, 0)
+    for d in (fused, plain):
+        d.load(s)
+        d.ctx.enc_prepare(d.st, n_m, h, F, d.out)
+    G.say("fused vs general launches,", case)
+    for step in range(6):
+        for d in (fused, plain):
+            d.ctx.step_enc(d.st, n_m, h, F, d.out)
+        a, b = fused.state(), plain.state()
+        for k in KEYS:
+            assert a[k].tobytes() == b[k].tobytes(), (step, k)
+        fa, pa = fused.out.to_host(), plain.out.to_host()
+        assert fa["acc"].tobytes() == pa["acc"].tobytes()
+        assert np.array_equal(fa["pair_i"], pa["pair_i"]) and fa["status"] == pa["status"]
+    fused.close()
+    plain.close()
