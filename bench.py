@@ -406,7 +406,9 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
         return e, L
 
     # eager steps on a copy, for the launch cost the graphs below remove
-    eager_n = min(2000, total)
+    chunks = 50
+    per = max(total // chunks, 1)
+    eager_n = per
     st_e = B.to_device_state(s0)
     ctx_e = B.Context(max_n=128, max_pairs=1 << 14)
     out_e = B.Outputs(100, 1 << 13)
@@ -437,10 +439,9 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
             step(st, ctx, out, stream=side)
     torch.cuda.synchronize()
     e0, L0 = invariants(s0)
-    chunks, worst_e, worst_l, skipped = 50, 0.0, 0.0, 0
-    per = max(total // chunks, 1)
+    worst_e, worst_l, skipped = 0.0, 0.0, 0
     t0 = time.perf_counter()
-    done = 0
+    done, first_rate = 0, None
     while done < total:
         k = min(per, total - done)
         for _ in range(k // graph_steps):
@@ -449,6 +450,10 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
             step(st, ctx, out)
         done += k
         torch.cuda.synchronize()
+        if first_rate is None:
+            # the same steps as the eager timing above (the cost of a step
+            # depends on how deep its encounters go, which changes over the run)
+            first_rate = done / (time.perf_counter() - t0)
         cur = {key: v.cpu().numpy() for key, v in st.items()}
         e, L = invariants(cur)
         worst_e = max(worst_e, abs(e - e0) / abs(e0))
@@ -461,11 +466,13 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
          "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
          "angmom_rel_err_max": worst_l, "checkpoints": chunks,
          "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
-         "steps_per_s": done / wall, "graph_steps": graph_steps, "eager_steps_per_s": eager_rate}
+         "steps_per_s": done / wall, "graph_steps": graph_steps,
+         "first_steps": {"steps": per, "graph_steps_per_s": first_rate, "eager_steps_per_s": eager_rate}}
     if encounters:
         r["checkpoints_with_unresolved_pairs"] = skipped
     log(f"accuracy disk, {label}: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s ({done / wall:.0f} "
-        f"steps/s in graphs of {graph_steps}, {eager_rate:.0f} eager), energy err max "
+        f"steps/s in graphs of {graph_steps}; first {per} steps {first_rate:.0f} steps/s in graphs, "
+        f"{eager_rate:.0f} eager), energy err max "
         f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}")
     ctx.close()
     return r
