@@ -57,35 +57,30 @@ __device__ __forceinline__ void partition(double x, double &f, double &df) {
     df = 140.0 * x3 * (u * u * u);
 }
 
-// F_k(r) and dF_k/dr; rk[j] = R_j of the pair.
-__device__ __forceinline__ void changeover(int k, double r, const double *rk, double &F, double &dF) {
-    if (k < 0) {
-        F = dF = 0.0;
-        return;
-    }
-    const double hi = rk[k], lo = rk[k + 1], w = hi - lo;
+// F(r) and dF/dr of the changeover between the shells hi = R_k and lo =
+// R_{k+1} (F_k of the pair).
+__device__ __forceinline__ void changeover(double r, double hi, double lo, double &F, double &dF) {
+    const double w = hi - lo;
     double f, df;
     partition((r - lo) / w, f, df);
     F = f;
     dF = df / w;
 }
 
-// W - r W' of level k for a pair at separation r with critical radius r0.
-__device__ __forceinline__ double force_factor(int k, double r, double r0) {
-    double rk[kEncMaxLevel + 2];
-    rk[0] = r0;
-#pragma unroll
-    for (int j = 1; j < kEncMaxLevel + 2; ++j) rk[j] = rk[j - 1] / kEncShellRatio;
+// W - r W' of level k for a pair at separation r whose shell radii are rm =
+// R_{k-1} (read for k >= 1), rk = R_k and rp = R_{k+1} (read for k < L);
+// F_{-1} = 0.
+__device__ __forceinline__ double force_factor(int k, double r, double rm, double rk, double rp) {
     double w, dw;
     if (k == kEncMaxLevel) {
         double F, dF;
-        changeover(k - 1, r, rk, F, dF);
+        changeover(r, rm, rk, F, dF);
         w = 1.0 - F;
         dw = -dF;
     } else {
-        double Fa, dFa, Fb, dFb;
-        changeover(k, r, rk, Fa, dFa);
-        changeover(k - 1, r, rk, Fb, dFb);
+        double Fa, dFa, Fb = 0.0, dFb = 0.0;
+        changeover(r, rk, rp, Fa, dFa);
+        if (k > 0) changeover(r, rm, rk, Fb, dFb);
         w = Fa - Fb;
         dw = dFa - dFb;
     }
@@ -226,6 +221,12 @@ struct GroupLds {
     int body[kEncGroupBodies];       // global index of each local body
     int pa[kEncGroupMaxPairs], pb[kEncGroupMaxPairs];  // local bodies of each pair (pa < pb globally)
     int depth[kEncGroupMaxPairs];    // deepest level the pair is in
+    int bdepth[kEncGroupBodies];     // deepest level of each body's pairs
+    double ax[kEncGroupBodies], ay[kEncGroupBodies], az[kEncGroupBodies];  // the last kick's accelerations
+    int akick[kEncGroupBodies];      // whether the last kick touched the body
+    // R_q of each pair, q = 0 .. L + 1: R_0 = rc_i + rc_j, then successive
+    // divisions by the shell ratio, once per step instead of in every kick
+    double rk[kEncMaxLevel + 2][kEncGroupMaxPairs];
     int ends[kEnds];
     int nb, np;
 };
@@ -324,35 +325,68 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
         G.np = np;
     }
     wave_sync();
+    if (full) {  // the shells of the recursion, and every body at level 1
+        for (int t = l; t < np; t += kGroupThreads) {
+            double r = G.rc[G.pa[t]] + G.rc[G.pb[t]];
+            G.rk[0][t] = r;
+            for (int q = 1; q < kEncMaxLevel + 2; ++q) {
+                r = r / kEncShellRatio;
+                G.rk[q][t] = r;
+            }
+        }
+        for (int b = l; b < nb; b += kGroupThreads) G.bdepth[b] = 1;
+        wave_sync();
+    }
     return true;
 }
 
-// Kick of level k for dt: each body's level-k pair forces summed in the
-// pairs' order, then v += dt a (bodies in no level-k pair are not touched).
-__device__ void kick(GroupLds &G, int k, double dt) {
+// Kick of level k for dt: each body's level-k acceleration (its level-k pair
+// forces summed in the pairs' order) times dt added to its velocity; bodies
+// in no level-k pair are not touched.  The accelerations are kept in LDS:
+// with `reuse` those of the previous kick are applied again, which the
+// caller passes only when no body has moved and no pair has changed level
+// since, so they are the values a new evaluation would give.  A pair at r
+// >= R_{k-1}, or at r <= R_{k+1} below the deepest level, has W_k = 0 and
+// W_k' = 0 exactly (both changeovers clip to the same end), so its force is
+// an exact zero and is not evaluated.
+__device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
     const int nb = G.nb, np = G.np;
     for (int b = lane(); b < nb; b += kGroupThreads) {
         double ax = 0.0, ay = 0.0, az = 0.0;
         bool any = false;
-        for (int t = 0; t < np; ++t) {
-            if (G.depth[t] < k) continue;
-            const int i = G.pa[t], j = G.pb[t];
-            if (i != b && j != b) continue;
-            any = true;
-            const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            const double g = force_factor(k, r, G.rc[i] + G.rc[j]) / (r * r * r);
-            if (b == i) {
-                const double s = G.m[j] * g;
-                ax += s * dx;
-                ay += s * dy;
-                az += s * dz;
-            } else {
-                const double s = G.m[i] * g;
-                ax -= s * dx;
-                ay -= s * dy;
-                az -= s * dz;
+        if (reuse) {
+            ax = G.ax[b];
+            ay = G.ay[b];
+            az = G.az[b];
+            any = G.akick[b] != 0;
+        } else {
+            for (int t = 0; t < np; ++t) {
+                if (G.depth[t] < k) continue;
+                const int i = G.pa[t], j = G.pb[t];
+                if (i != b && j != b) continue;
+                any = true;
+                const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
+                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double rm = G.rk[k - 1][t], rk = G.rk[k][t], rp = G.rk[k + 1][t];
+                const bool ordered = rp < rk && rk < rm;
+                if (ordered && (r >= rm || (k < kEncMaxLevel && r <= rp))) continue;
+                const double g = force_factor(k, r, rm, rk, rp) / (r * r * r);
+                if (b == i) {
+                    const double s = G.m[j] * g;
+                    ax += s * dx;
+                    ay += s * dy;
+                    az += s * dz;
+                } else {
+                    const double s = G.m[i] * g;
+                    ax -= s * dx;
+                    ay -= s * dy;
+                    az -= s * dz;
+                }
             }
+            G.ax[b] = ax;
+            G.ay[b] = ay;
+            G.az[b] = az;
+            G.akick[b] = any;
         }
         if (any) {
             G.vx[b] += dt * ax;
@@ -370,24 +404,28 @@ __device__ bool check(GroupLds &G, int k, double tau) {
     for (int t = lane(); t < G.np; t += kGroupThreads) {
         if (G.depth[t] < k) continue;
         const int i = G.pa[t], j = G.pb[t];
-        double radius = G.rc[i] + G.rc[j];
-        for (int q = 0; q < k; ++q) radius = radius / kEncShellRatio;
         const bool fl = encounter(G.x[j] - G.x[i], G.y[j] - G.y[i], G.z[j] - G.z[i], G.vx[j] - G.vx[i],
-                                  G.vy[j] - G.vy[i], G.vz[j] - G.vz[i], radius, tau);
+                                  G.vy[j] - G.vy[i], G.vz[j] - G.vz[i], G.rk[k][t], tau);
         G.depth[t] = fl ? k + 1 : k;
         any = any || fl;
     }
+    // each body's deepest level, for the drift
+    for (int b = lane(); b < G.nb; b += kGroupThreads) G.bdepth[b] = 0;
+    wave_sync();
+    for (int t = lane(); t < G.np; t += kGroupThreads) {
+        atomicMax(&G.bdepth[G.pa[t]], G.depth[t]);
+        atomicMax(&G.bdepth[G.pb[t]], G.depth[t]);
+    }
+    wave_sync();
     return __ballot(any) != 0;
 }
 
 // Kepler drift for tau of the bodies whose deepest pair is at level k
 // (exactly k, or at least k when `at_least`).
 __device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
-    const int nb = G.nb, np = G.np;
+    const int nb = G.nb;
     for (int b = lane(); b < nb; b += kGroupThreads) {
-        int d = -1;
-        for (int t = 0; t < np; ++t)
-            if (G.pa[t] == b || G.pb[t] == b) d = max(d, G.depth[t]);
+        const int d = G.bdepth[b];
         if (at_least ? d < k : d != k) continue;
         double x = G.x[b], y = G.y[b], z = G.z[b], vx = G.vx[b], vy = G.vy[b], vz = G.vz[b];
         kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
@@ -409,10 +447,15 @@ __device__ void integrate(GroupLds &G, double h) {
     int k = 1;
     sub[1] = 0;
     bool enter = true;
+    // the level whose accelerations the last kick left in LDS, while no body
+    // has drifted since: a substep's closing kick and the next substep's
+    // opening kick at the same level see the same positions and pairs
+    int cached = -1;
     while (true) {
         const double tau = ldexp(h, -2 * k);  // h / M^k, M = 4
         if (enter) {
-            kick(G, k, 0.5 * tau);
+            kick(G, k, 0.5 * tau, cached == k);
+            cached = -1;  // a drift follows
             if (k == kEncMaxLevel) {
                 drift(G, k, tau, true);
                 enter = false;
@@ -425,7 +468,8 @@ __device__ void integrate(GroupLds &G, double h) {
                 enter = false;
             }
         } else {
-            kick(G, k, 0.5 * tau);
+            kick(G, k, 0.5 * tau, false);
+            cached = k;
             if (++sub[k] < kEncSub) {
                 enter = true;
             } else if (k == 1) {
@@ -453,7 +497,7 @@ __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
             const double r0 = G.rc[i] + G.rc[j];
             if (r >= r0) continue;
             any = true;
-            const double gf = (force_factor(0, r, r0) - 1.0) / (r * r * r);
+            const double gf = (force_factor(0, r, 0.0, r0, r0 / kEncShellRatio) - 1.0) / (r * r * r);
             if (b == i) {
                 const double s = G.m[j] * gf;
                 ax += s * dx;
@@ -524,14 +568,14 @@ __global__ __launch_bounds__(256) void k_enc_kick(const EncDesc e) {
 // A problem of one block (n <= 256 bodies): the step's work before the
 // evaluation in one launch.  The first kick with the momentum's block sum,
 // the table (bodies of resolved groups marked), the Sun drift of every body
-// and the Kepler drift of the unmarked ones, the groups (wave w takes groups
-// w, w + 4, ...), then the momentum and the second Sun drift: the operations
+// and the Kepler drift of the unmarked ones, the groups (wave w < 3 takes
+// groups w, w + 3, ...), then the momentum and the second Sun drift: the operations
 // of the separate launches in the same order, on the same values.
 constexpr int kFusedThreads = 256;
-constexpr int kFusedWaves = kFusedThreads / kWave;
+constexpr int kFusedGroups = 3;  // waves that take groups (three groups' LDS fit beside the rest)
 union FusedLds {
     unsigned long long key[kEncMaxPairs];
-    GroupLds G[kFusedWaves];
+    GroupLds G[kFusedGroups];
 };
 
 __global__ __launch_bounds__(kFusedThreads) void k_enc_drifts_block(const StepDesc one, const EncDesc e) {
@@ -544,7 +588,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_enc_drifts_block(const StepDe
     __syncthreads();  // every body's Sun drift (and Kepler drift) is in memory
     const int w = threadIdx.x / kWave;
     const int ng = e.ctl[kEncCtlGroups];
-    for (int g = w; g < ng; g += kFusedWaves) drift_group(e, U.G[w], g);
+    if (w < kFusedGroups)
+        for (int g = w; g < ng; g += kFusedGroups) drift_group(e, U.G[w], g);
     __syncthreads();  // the groups' bodies are back in memory
     const int64_t k = drift::body_of(one);
     double vx = 0.0, vy = 0.0, vz = 0.0;
@@ -558,15 +603,16 @@ __global__ __launch_bounds__(kFusedThreads) void k_enc_drifts_block(const StepDe
 }
 
 // A problem of one block: the step's work after the evaluation in one
-// launch: the table of the new pairs, the level-0 reweighting (wave w takes
-// groups w, w + 4, ...), the closing kick and the status.
+// launch: the table of the new pairs, the level-0 reweighting (wave w < 3
+// takes groups w, w + 3, ...), the closing kick and the status.
 __global__ __launch_bounds__(kFusedThreads) void k_enc_post_block(const EncDesc e) {
     __shared__ FusedLds U;
     build_table<kFusedThreads>(e, U.key);
     __syncthreads();
     const int w = threadIdx.x / kWave;
     const int ng = e.ctl[kEncCtlGroups];
-    for (int g = w; g < ng; g += kFusedWaves) level0_group(e, U.G[w], g);
+    if (w < kFusedGroups)
+        for (int g = w; g < ng; g += kFusedGroups) level0_group(e, U.G[w], g);
     __syncthreads();
     const int64_t k = threadIdx.x;
     if (e.kick_h != 0.0 && k < e.n) {
