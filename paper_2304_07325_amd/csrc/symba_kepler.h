@@ -89,7 +89,11 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
         const double root = sqrt(fabs(16.0 * dF * dF - 20.0 * F * ddF));
         const double ds = -5.0 * F / (dF + (dF >= 0.0 ? root : -root));
         s += ds;
-        if (!(fabs(ds) > 1e-15 * fabs(s))) break;  // converged (or NaN input)
+        // converged (or NaN input).  Near the root the iteration is cubic: a
+        // correction below 1e-7 |s| leaves an error of order 1e-21 |s|, so a
+        // short arc (the encounter substeps, the accuracy disk's steps) stops
+        // after one iteration instead of a second that would only confirm it
+        if (!(fabs(ds) > 1e-7 * fabs(s))) break;
     }
     stumpff(beta * s * s, c0, c1, c2, c3);
     const double r = r0 * c0 + s * (eta * c1 + s * c2);
