@@ -186,6 +186,10 @@ def main():
     ap.add_argument("--no-step", action="store_true", help="skip the full-step (drifts + evaluation) legs")
     ap.add_argument("--accuracy-years", type=float, default=1e4,
                     help="length of the accuracy-disk integration of the step leg")
+    ap.add_argument("--paper-steps", type=int, default=200,
+                    help="encounter steps on each of the paper's 1k, 2k, 5k and 10k disks (0: skip)")
+    ap.add_argument("--paper-budget-s", type=float, default=8.0,
+                    help="wall-time cap per disk of those runs")
     ap.add_argument("--no-hot-check", action="store_true",
                     help="skip the oracle check of one 50k hot-disk evaluation (about 20 s of host time)")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -362,6 +366,80 @@ def bench_step(args, B, dg, torch):
     acc_disk = dg.make_accuracy_disk(n=100)
     res["accuracy_disk"] = accuracy_run(args, B, dg, torch, acc_disk, encounters=False)
     res["accuracy_disk_enc"] = accuracy_run(args, B, dg, torch, acc_disk, encounters=True)
+    if args.paper_steps > 0:
+        res["paper_disks_enc"] = paper_disk_runs(args, B, dg, torch)
+    return res
+
+
+def split_energy(st, torch):
+    """Energy of the split Hamiltonian (Kepler + Sun + interaction terms,
+    heliocentric positions, barycentric velocities) and angular momentum of a
+    device state, in FP64 on the GPU (the pair sum in row blocks)."""
+    x = torch.stack([st["x"], st["y"], st["z"]], 1)
+    v = torch.stack([st["vx"], st["vy"], st["vz"]], 1)
+    m = st["m"]
+    p = (m[:, None] * v).sum(0)
+    e = float((0.5 * m * (v * v).sum(1) - m / x.norm(dim=1)).sum() + 0.5 * (p @ p))
+    n = x.shape[0]
+    idx = torch.arange(n, device=x.device)
+    pot = 0.0
+    for i0 in range(0, n, 1024):
+        i1 = min(i0 + 1024, n)
+        r = (x[i0:i1, None, :] - x[None, :, :]).norm(dim=2)
+        upper = idx[None, :] > idx[i0:i1, None]
+        mm = m[i0:i1, None] * m[None, :]
+        pot += float(torch.where(upper, mm / torch.where(upper, r, torch.ones_like(r)), torch.zeros_like(r)).sum())
+    L = (m[:, None] * torch.linalg.cross(x, v)).sum(0)
+    return e - pot, L
+
+
+def paper_disk_runs(args, B, dg, torch):
+    """The encounter step (symba_step_enc) on the paper's four benchmark
+    disks (Sec. 3: 1k, 2k, 5k and 10k cold planetesimal disks, 0.5-year
+    steps): `--paper-steps` steps of each (or `--paper-budget-s` seconds),
+    each step timed on its own, since a step lasts as long as its deepest
+    encounter group's chain of substeps.  Reported with the projected time of
+    the paper's 1e4-year runs (20,000 steps) at the measured mean."""
+    import numpy as np
+    f, h = dg.RCRIT_FACTOR, dg.DT_HALF_YEAR
+    res = {}
+    for name in ("disk1k", "disk2k", "disk5k", "disk10k"):
+        w = dg.WORKLOADS[name]
+        n, n_m = w["n"], w["n_massive"]
+        disk = dg.make_disk(n, n_m, w["kind"], w["seed"])
+        st = B.to_device_state(disk.state(0))
+        ctx = B.Context(max_n=n, max_pairs=1 << 16)
+        out = B.Outputs(n, 1 << 14)
+        e0, L0 = split_energy(st, torch)
+        ctx.enc_prepare(st, n_m, h, f, out)
+        torch.cuda.synchronize()
+        ctx.read_stats()
+        ts, skipped = [], 0
+        t_start = time.perf_counter()
+        for _ in range(args.paper_steps):
+            t0 = time.perf_counter()
+            ctx.step_enc(st, n_m, h, f, out)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            skipped += bool(int(out.scalars32[1].item()) & B.STATUS_ENC_SKIPPED)
+            if time.perf_counter() - t_start > args.paper_budget_s:
+                break
+        _, flagged, calls = ctx.read_stats()
+        e1, L1 = split_energy(st, torch)
+        ms = np.array(ts) * 1e3
+        r = {"n": n, "n_m": n_m, "steps": len(ts), "years": len(ts) * h / dg.YEAR,
+             "steps_per_s": len(ts) / float(np.sum(ts)), "ms_per_step": percentiles(ms),
+             "ms_per_step_mean": float(ms.mean()),
+             "projected_s_for_1e4_years": float(ms.mean()) * 1e-3 * round(1e4 * dg.YEAR / h),
+             "encounter_pairs_per_step": flagged / max(calls, 1), "steps_with_unresolved_pairs": skipped,
+             "energy_rel_err_end": abs(e1 - e0) / abs(e0),
+             "angmom_rel_err_end": float((L1 - L0).norm() / L0.norm())}
+        res[name] = r
+        log(f"paper disk {name}, encounter step: {len(ts)} steps, {r['steps_per_s']:.1f} steps/s, mean "
+            f"{r['ms_per_step_mean']:.2f} ms (p50 {r['ms_per_step']['p50']:.2f}, p99 {r['ms_per_step']['p99']:.2f}), "
+            f"{r['encounter_pairs_per_step']:.0f} flagged pairs/step, 1e4 yr projected "
+            f"{r['projected_s_for_1e4_years']:.0f} s, energy err {r['energy_rel_err_end']:.2e}")
+        ctx.close()
     return res
 
 

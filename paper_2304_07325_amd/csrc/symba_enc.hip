@@ -37,6 +37,7 @@ constexpr int kStatusEncSkipped = 4;      // SYMBA_STATUS_ENC_SKIPPED
 constexpr int kStatusCapacityBit = 1;     // SYMBA_STATUS_CAPACITY
 
 static_assert((kEnds & (kEnds - 1)) == 0, "the endpoint sort needs a power of two");
+static_assert(kEncSub == 4 && 2 * (kEncMaxLevel + 1) <= 32, "substep counters: two bits per level");
 static_assert((kEncMaxPairs & (kEncMaxPairs - 1)) == 0, "the table sort needs a power of two");
 
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
@@ -49,17 +50,27 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// f_3 and its derivative at x clipped to [0, 1].
+// The arithmetic of the group integration spells out every fused
+// multiply-add (no contraction left to the compiler), so that a value does
+// not depend on where the compiler inlined it: the routines for groups of any
+// size and the register path for one pair give the same bits.
+
+// f_3 and its derivative at x clipped to [0, 1] (f_3 = 1 and f_3' = 0 exactly
+// at x = 1, 0 and 0 at x = 0).
 __device__ __forceinline__ void partition(double x, double &f, double &df) {
+#pragma clang fp contract(off)
     x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
     const double x2 = x * x, x3 = x2 * x, u = 1.0 - x;
-    f = x3 * x * (35.0 - 84.0 * x + 70.0 * x2 - 20.0 * x3);
+    // 35 - 84 x + 70 x^2 - 20 x^3 in Horner form
+    const double p = __builtin_fma(__builtin_fma(__builtin_fma(-20.0, x, 70.0), x, -84.0), x, 35.0);
+    f = x3 * x * p;
     df = 140.0 * x3 * (u * u * u);
 }
 
 // F(r) and dF/dr of the changeover between the shells hi = R_k and lo =
 // R_{k+1} (F_k of the pair).
 __device__ __forceinline__ void changeover(double r, double hi, double lo, double &F, double &dF) {
+#pragma clang fp contract(off)
     const double w = hi - lo;
     double f, df;
     partition((r - lo) / w, f, df);
@@ -71,6 +82,7 @@ __device__ __forceinline__ void changeover(double r, double hi, double lo, doubl
 // R_{k-1} (read for k >= 1), rk = R_k and rp = R_{k+1} (read for k < L);
 // F_{-1} = 0.
 __device__ __forceinline__ double force_factor(int k, double r, double rm, double rk, double rp) {
+#pragma clang fp contract(off)
     double w, dw;
     if (k == kEncMaxLevel) {
         double F, dF;
@@ -84,7 +96,7 @@ __device__ __forceinline__ double force_factor(int k, double r, double rm, doubl
         w = Fa - Fb;
         dw = dFa - dFb;
     }
-    return w - r * dw;
+    return __builtin_fma(-r, dw, w);
 }
 
 // The close-encounter test with radius `radius` over an interval tau (for tau
@@ -92,19 +104,20 @@ __device__ __forceinline__ double force_factor(int k, double r, double rm, doubl
 // extrapolated end, or a closest approach inside the interval.
 __device__ __forceinline__ bool encounter(double dx, double dy, double dz, double wx, double wy, double wz,
                                           double radius, double tau) {
+#pragma clang fp contract(off)
     if (tau < 0.0) {
         wx = -wx;
         wy = -wy;
         wz = -wz;
         tau = -tau;
     }
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const double v2 = wx * wx + wy * wy + wz * wz;
-    const double vr = dx * wx + dy * wy + dz * wz;
+    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+    const double v2 = __builtin_fma(wz, wz, __builtin_fma(wy, wy, wx * wx));
+    const double vr = __builtin_fma(dz, wz, __builtin_fma(dy, wy, dx * wx));
     const double rc2 = radius * radius;
     if (r2 < rc2) return true;
-    if (r2 + 2.0 * vr * tau + v2 * tau * tau < rc2) return true;
-    if (vr < 0.0 && -vr < v2 * tau) return r2 * v2 - vr * vr < rc2 * v2;
+    if (__builtin_fma(v2 * tau, tau, __builtin_fma(2.0 * vr, tau, r2)) < rc2) return true;
+    if (vr < 0.0 && -vr < v2 * tau) return __builtin_fma(-vr, vr, r2 * v2) < rc2 * v2;
     return false;
 }
 
@@ -350,6 +363,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
 // W_k' = 0 exactly (both changeovers clip to the same end), so its force is
 // an exact zero and is not evaluated.
 __device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
+#pragma clang fp contract(off)
     const int nb = G.nb, np = G.np;
     for (int b = lane(); b < nb; b += kGroupThreads) {
         double ax = 0.0, ay = 0.0, az = 0.0;
@@ -366,21 +380,21 @@ __device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
                 if (i != b && j != b) continue;
                 any = true;
                 const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
-                const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
                 const double rm = G.rk[k - 1][t], rk = G.rk[k][t], rp = G.rk[k + 1][t];
                 const bool ordered = rp < rk && rk < rm;
                 if (ordered && (r >= rm || (k < kEncMaxLevel && r <= rp))) continue;
                 const double g = force_factor(k, r, rm, rk, rp) / (r * r * r);
                 if (b == i) {
                     const double s = G.m[j] * g;
-                    ax += s * dx;
-                    ay += s * dy;
-                    az += s * dz;
+                    ax = __builtin_fma(s, dx, ax);
+                    ay = __builtin_fma(s, dy, ay);
+                    az = __builtin_fma(s, dz, az);
                 } else {
                     const double s = G.m[i] * g;
-                    ax -= s * dx;
-                    ay -= s * dy;
-                    az -= s * dz;
+                    ax = __builtin_fma(-s, dx, ax);
+                    ay = __builtin_fma(-s, dy, ay);
+                    az = __builtin_fma(-s, dz, az);
                 }
             }
             G.ax[b] = ax;
@@ -389,9 +403,9 @@ __device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
             G.akick[b] = any;
         }
         if (any) {
-            G.vx[b] += dt * ax;
-            G.vy[b] += dt * ay;
-            G.vz[b] += dt * az;
+            G.vx[b] = __builtin_fma(dt, ax, G.vx[b]);
+            G.vy[b] = __builtin_fma(dt, ay, G.vy[b]);
+            G.vz[b] = __builtin_fma(dt, az, G.vz[b]);
         }
     }
     wave_sync();
@@ -443,9 +457,8 @@ __device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
 // its pairs need.  The loop visits (level, substep) in the order of the
 // recursion; every wave reaches its end after at most sum_k M^k substeps.
 __device__ void integrate(GroupLds &G, double h) {
-    int sub[kEncMaxLevel + 1];
+    unsigned subs = 0;  // substeps done at each level, two bits per level (M = 4)
     int k = 1;
-    sub[1] = 0;
     bool enter = true;
     // the level whose accelerations the last kick left in LDS, while no body
     // has drifted since: a substep's closing kick and the next substep's
@@ -462,7 +475,7 @@ __device__ void integrate(GroupLds &G, double h) {
             } else if (check(G, k, tau)) {
                 drift(G, k, tau, false);
                 ++k;
-                sub[k] = 0;
+                subs &= ~(3u << (2 * k));
             } else {
                 drift(G, k, tau, false);
                 enter = false;
@@ -470,7 +483,9 @@ __device__ void integrate(GroupLds &G, double h) {
         } else {
             kick(G, k, 0.5 * tau, false);
             cached = k;
-            if (++sub[k] < kEncSub) {
+            const unsigned done = ((subs >> (2 * k)) & 3u) + 1u;
+            subs = (subs & ~(3u << (2 * k))) | ((done & 3u) << (2 * k));
+            if (done < (unsigned)kEncSub) {
                 enter = true;
             } else if (k == 1) {
                 break;
@@ -485,6 +500,7 @@ __device__ void integrate(GroupLds &G, double h) {
 // m (F_0 - r F_0' - 1) (x_j - x_i) / r^3 on i and its opposite on j, summed
 // per body in the pairs' order and added to the Newtonian sums.  One wave.
 __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
+#pragma clang fp contract(off)
     if (e.gskip[g] || !load_group(e, G, g, false)) return;
     for (int b = lane(); b < G.nb; b += kGroupThreads) {
         double ax = 0.0, ay = 0.0, az = 0.0;
@@ -493,21 +509,21 @@ __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
             const int i = G.pa[t], j = G.pb[t];
             if (i != b && j != b) continue;
             const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
             const double r0 = G.rc[i] + G.rc[j];
             if (r >= r0) continue;
             any = true;
             const double gf = (force_factor(0, r, 0.0, r0, r0 / kEncShellRatio) - 1.0) / (r * r * r);
             if (b == i) {
                 const double s = G.m[j] * gf;
-                ax += s * dx;
-                ay += s * dy;
-                az += s * dz;
+                ax = __builtin_fma(s, dx, ax);
+                ay = __builtin_fma(s, dy, ay);
+                az = __builtin_fma(s, dz, az);
             } else {
                 const double s = G.m[i] * gf;
-                ax -= s * dx;
-                ay -= s * dy;
-                az -= s * dz;
+                ax = __builtin_fma(-s, dx, ax);
+                ay = __builtin_fma(-s, dy, ay);
+                az = __builtin_fma(-s, dz, az);
             }
         }
         if (any) {
@@ -520,10 +536,142 @@ __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
     wave_sync();
 }
 
+// The value of lane l ^ 1 (DPP quad_perm [1, 0, 3, 2]: lanes 0 and 1 swap).
+__device__ __forceinline__ double swap_pair(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xb1, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xb1, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// A group of one pair, the common case of the deep recursions: integrate()
+// with the two bodies in registers, body i of the pair in the even lanes and
+// body j in the odd ones (every lane pair holds the same two), each lane
+// reading its partner through a lane swap instead of LDS.  The same
+// operations on the same values as the LDS routines (kick, check, drift with
+// a single pair), so the same bits.
+__device__ void drift_pair(const EncDesc &e, int g) {
+#pragma clang fp contract(off)
+    const int p = e.gp[e.gstart[g]];
+    const bool first = (lane() & 1) == 0;
+    const int b = first ? e.pair_i[p] : e.pair_j[p];
+    double x = e.x[b], y = e.y[b], z = e.z[b], vx = e.vx[b], vy = e.vy[b], vz = e.vz[b];
+    const double m_other = swap_pair(b < e.n_tri ? e.m[b] : 0.0);
+    double R[kEncMaxLevel + 2];  // the pair's shells, as load_group computes them
+    {
+        const double rc = e.f * e.rh[b];  // rc_i + rc_j of the rounded products, as load_group adds them
+        const double rc_other = swap_pair(rc);
+        double r = first ? rc + rc_other : rc_other + rc;
+#pragma unroll
+        for (int q = 0; q < kEncMaxLevel + 2; ++q) {
+            if (q > 0) r = r / kEncShellRatio;
+            R[q] = r;
+        }
+    }
+    const double h = e.h;
+    int depth = 1;  // the pair's deepest level
+    double cax = 0.0, cay = 0.0, caz = 0.0;  // the last kick's acceleration
+    bool cany = false;
+    unsigned subs = 0;  // substeps done at each level, two bits per level
+    int k = 1;
+    bool enter = true;
+    int cached = -1;
+    while (true) {
+        const double tau = ldexp(h, -2 * k);
+        double rm = R[0], rk = R[1], rp = R[2];  // R_{k-1}, R_k, R_{k+1}
+#pragma unroll
+        for (int q = 2; q <= kEncMaxLevel; ++q)
+            if (k == q) {
+                rm = R[q - 1];
+                rk = R[q];
+                rp = R[q + 1];
+            }
+        // kick of level k for tau / 2 (the pair's force at level k, nothing
+        // below it), the accelerations of the last kick again when no body
+        // has drifted since it at this level
+        if (!(enter && cached == k)) {
+            cax = cay = caz = 0.0;
+            cany = depth >= k;
+            if (cany) {
+                const double xo = swap_pair(x), yo = swap_pair(y), zo = swap_pair(z);
+                const double dx = first ? xo - x : x - xo, dy = first ? yo - y : y - yo,
+                             dz = first ? zo - z : z - zo;
+                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+                const bool ordered = rp < rk && rk < rm;
+                if (!(ordered && (r >= rm || (k < kEncMaxLevel && r <= rp)))) {
+                    const double gf = force_factor(k, r, rm, rk, rp) / (r * r * r);
+                    const double s = m_other * gf;
+                    if (first) {
+                        cax = __builtin_fma(s, dx, cax);
+                        cay = __builtin_fma(s, dy, cay);
+                        caz = __builtin_fma(s, dz, caz);
+                    } else {
+                        cax = __builtin_fma(-s, dx, cax);
+                        cay = __builtin_fma(-s, dy, cay);
+                        caz = __builtin_fma(-s, dz, caz);
+                    }
+                }
+            }
+        }
+        if (cany) {
+            const double dt = 0.5 * tau;
+            vx = __builtin_fma(dt, cax, vx);
+            vy = __builtin_fma(dt, cay, vy);
+            vz = __builtin_fma(dt, caz, vz);
+        }
+        if (enter) {
+            cached = -1;
+            if (k == kEncMaxLevel) {
+                if (depth >= k) kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
+                enter = false;
+            } else {
+                // the level-k test over tau: the pair goes to level k + 1 or
+                // stays at k; every lane tests the same values, lane 0 decides
+                const double xo = swap_pair(x), yo = swap_pair(y), zo = swap_pair(z);
+                const double vxo = swap_pair(vx), vyo = swap_pair(vy), vzo = swap_pair(vz);
+                const bool fl = first ? encounter(xo - x, yo - y, zo - z, vxo - vx, vyo - vy, vzo - vz, rk, tau)
+                                      : encounter(x - xo, y - yo, z - zo, vx - vxo, vy - vyo, vz - vzo, rk, tau);
+                depth = __builtin_amdgcn_readfirstlane(fl ? k + 1 : k);
+                if (depth > k) {
+                    ++k;
+                    subs &= ~(3u << (2 * k));
+                } else {
+                    kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
+                    enter = false;
+                }
+            }
+        } else {
+            cached = k;
+            const unsigned done = ((subs >> (2 * k)) & 3u) + 1u;
+            subs = (subs & ~(3u << (2 * k))) | ((done & 3u) << (2 * k));
+            if (done < (unsigned)kEncSub) {
+                enter = true;
+            } else if (k == 1) {
+                break;
+            } else {
+                --k;
+            }
+        }
+    }
+    if (lane() < 2) {
+        e.x[b] = x;
+        e.y[b] = y;
+        e.z[b] = z;
+        e.vx[b] = vx;
+        e.vy[b] = vy;
+        e.vz[b] = vz;
+        e.ingroup[b] = 0;
+    }
+}
+
 // One group's drift over the step, from its bodies in memory back to them
 // (the table marked them, so the drift kernels left them alone).  One wave.
 __device__ void drift_group(const EncDesc &e, GroupLds &G, int g) {
-    if (e.gskip[g] || !load_group(e, G, g, true)) return;
+    if (e.gskip[g]) return;
+    if (e.pair_regs && e.gstart[g + 1] - e.gstart[g] == 1) {
+        drift_pair(e, g);
+        return;
+    }
+    if (!load_group(e, G, g, true)) return;
     integrate(G, e.h);
     for (int b = lane(); b < G.nb; b += kGroupThreads) {
         const int k = G.body[b];

@@ -36,6 +36,7 @@ constexpr StumpffCoeffs kStumpff = make_stumpff_coeffs();
 // Horner form, one FMA per term with no division on the solver's critical
 // path, then c0 = 1 - x c2 and c1 = 1 - x c3.
 __device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double &c2, double &c3) {
+#pragma clang fp contract(off)
     if (fabs(x) < 1.0) {
         const double y = -x;
         double s2 = kStumpff.c2[kStumpffTerms - 1], s3 = kStumpff.c3[kStumpffTerms - 1];
@@ -46,8 +47,8 @@ __device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double
         }
         c2 = s2;
         c3 = s3;
-        c0 = 1.0 - x * c2;
-        c1 = 1.0 - x * c3;
+        c0 = __builtin_fma(-x, c2, 1.0);
+        c1 = __builtin_fma(-x, c3, 1.0);
     } else if (x > 0.0) {
         const double q = sqrt(x), sn = sin(q), cs = cos(q);
         c0 = cs;
@@ -70,10 +71,13 @@ __device__ __forceinline__ void stumpff(double x, double &c0, double &c1, double
 // f = 1 - s^2 c2 / r0, g = h - s^3 c3, fdot = -s c1 / (r r0), gdot = 1 - s^2 c2 / r.
 __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, double &vx, double &vy, double &vz,
                                              double h) {
-    const double r0 = sqrt(x * x + y * y + z * z);
-    const double beta = 2.0 / r0 - (vx * vx + vy * vy + vz * vz);
-    const double eta = x * vx + y * vy + z * vz;
-    const double zeta = 1.0 - beta * r0;
+    // every fused multiply-add spelled out, so the drift of a body gives the
+    // same bits wherever the compiler inlines it
+#pragma clang fp contract(off)
+    const double r0 = sqrt(__builtin_fma(z, z, __builtin_fma(y, y, x * x)));
+    const double beta = 2.0 / r0 - __builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx));
+    const double eta = __builtin_fma(z, vz, __builtin_fma(y, vy, x * vx));
+    const double zeta = __builtin_fma(-beta, r0, 1.0);
     // first guess: h / r0 for short arcs and ellipses; on a hyperbola the
     // variable grows like log(v_inf t) / v_inf (r ~ v_inf t far out)
     double s = h / r0, c0, c1, c2, c3;
@@ -83,10 +87,10 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
     }
     for (int it = 0; it < 40; ++it) {
         stumpff(beta * s * s, c0, c1, c2, c3);
-        const double F = s * (r0 * c1 + s * (eta * c2 + s * c3)) - h;
-        const double dF = r0 * c0 + s * (eta * c1 + s * c2);
-        const double ddF = eta * c0 + zeta * s * c1;
-        const double root = sqrt(fabs(16.0 * dF * dF - 20.0 * F * ddF));
+        const double F = __builtin_fma(s, __builtin_fma(s, __builtin_fma(s, c3, eta * c2), r0 * c1), -h);
+        const double dF = __builtin_fma(s, __builtin_fma(s, c2, eta * c1), r0 * c0);
+        const double ddF = __builtin_fma(zeta * s, c1, eta * c0);
+        const double root = sqrt(fabs(__builtin_fma(16.0 * dF, dF, -20.0 * F * ddF)));
         const double ds = -5.0 * F / (dF + (dF >= 0.0 ? root : -root));
         s += ds;
         // converged (or NaN input).  Near the root the iteration is cubic: a
@@ -96,14 +100,16 @@ __device__ __forceinline__ void kepler_drift(double &x, double &y, double &z, do
         if (!(fabs(ds) > 1e-7 * fabs(s))) break;
     }
     stumpff(beta * s * s, c0, c1, c2, c3);
-    const double r = r0 * c0 + s * (eta * c1 + s * c2);
+    const double r = __builtin_fma(s, __builtin_fma(s, c2, eta * c1), r0 * c0);
     const double inv_r0 = 1.0 / r0, inv_r = 1.0 / r;
-    const double f = 1.0 - s * s * c2 * inv_r0, g = h - s * s * s * c3;
-    const double fd = -s * c1 * inv_r0 * inv_r, gd = 1.0 - s * s * c2 * inv_r;
-    const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
-    vx = fd * x + gd * vx;
-    vy = fd * y + gd * vy;
-    vz = fd * z + gd * vz;
+    const double s2c2 = s * s * c2;
+    const double f = __builtin_fma(-s2c2, inv_r0, 1.0), g = __builtin_fma(-(s * s * s), c3, h);
+    const double fd = -s * c1 * inv_r0 * inv_r, gd = __builtin_fma(-s2c2, inv_r, 1.0);
+    const double nx = __builtin_fma(f, x, g * vx), ny = __builtin_fma(f, y, g * vy),
+                 nz = __builtin_fma(f, z, g * vz);
+    vx = __builtin_fma(fd, x, gd * vx);
+    vy = __builtin_fma(fd, y, gd * vy);
+    vz = __builtin_fma(fd, z, gd * vz);
     x = nx;
     y = ny;
     z = nz;

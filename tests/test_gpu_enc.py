@@ -404,3 +404,105 @@ def test_fused_small_problem_launches_are_bit_identical(case):
         assert np.array_equal(fa["pair_i"], pa["pair_i"]) and fa["status"] == pa["status"]
     fused.close()
     plain.close()
+
+
+def _binary(extra=0):
+    """A tight binary (two 3e-8 solar-mass bodies 2e-5 AU apart on a mutual
+    circular orbit, well inside the deepest shell) on a 10 AU orbit, plus
+    `extra` far-apart bodies on a wide ring: the pair stays at level 8 for
+    the whole step (4^8 substeps at that level)."""
+    m, a, sep = 3e-8, 10.0, 2e-5
+    vc, vb = math.sqrt(1.0 / a), math.sqrt(2 * m / sep) / 2
+    x = [[a - sep / 2, 0.0, 0.0], [a + sep / 2, 0.0, 0.0]]
+    v = [[0.0, vc - vb, 0.0], [0.0, vc + vb, 0.0]]
+    for k in range(extra):
+        th, r = 2 * math.pi * (k + 1) / (extra + 2), 6.0 + 10.0 * k / max(extra, 1)
+        x.append([r * math.cos(th), r * math.sin(th), 0.0])
+        v.append([-math.sin(th) / math.sqrt(r), math.cos(th) / math.sqrt(r), 0.0])
+    return _state(x, v, [m] * (2 + extra))
+
+
+@pytest.mark.parametrize("case", ["flyby", "binary", "binary_wide", "disk1k"])
+def test_one_pair_groups_in_registers_are_bit_identical(case):
+    """Groups of one pair run with their two bodies in registers
+    (SYMBA_OPT_ENC_PAIR = 1); the routines for groups of any size
+    (SYMBA_OPT_ENC_PAIR = 0) give the same bits: a fast flyby, a tight binary
+    at the deepest level for the whole step (one block, and 300 bodies through
+    the general launches), and 20 steps of the paper's 1k disk (groups of one
+    pair and larger ones in the same launch)."""
+    from paper_2304_07325_amd import binding as B
+    if case == "flyby":
+        x, v, m = _flyby(sep=0.15)
+        s, n_m, h, steps = _state(x, v, m), 2, 0.025, 6
+    elif case == "binary":
+        s, n_m, h, steps = _binary(), 2, dg.DT_HALF_YEAR, 1
+    elif case == "binary_wide":
+        s, n_m, h, steps = _binary(298), 300, dg.DT_HALF_YEAR, 1
+    else:
+        w = dg.WORKLOADS["disk1k"]
+        s = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"]).state(0)
+        n_m, h, steps = w["n_massive"], dg.DT_HALF_YEAR, 20
+    n = s["x"].size
+    regs, lds = Dev(n), Dev(n)
+    lds.ctx.set_option(B.OPT_ENC_PAIR, 0)
+    for d in (regs, lds):
+        d.load(s)
+        d.ctx.enc_prepare(d.st, n_m, h, F, d.out)
+    G.say("one-pair groups in registers vs LDS,", case)
+    for step in range(steps):
+        for d in (regs, lds):
+            d.ctx.step_enc(d.st, n_m, h, F, d.out)
+        a, b = regs.state(), lds.state()
+        for k in KEYS:
+            assert a[k].tobytes() == b[k].tobytes(), (step, k)
+        ra, la = regs.out.to_host(), lds.out.to_host()
+        assert ra["acc"].tobytes() == la["acc"].tobytes()
+        assert ra["status"] == la["status"] == 0
+        assert np.array_equal(ra["pair_i"], la["pair_i"]) and np.array_equal(ra["pair_j"], la["pair_j"])
+    if case.startswith("binary"):
+        assert regs.out.to_host()["n_pairs"] >= 1   # still a pair, deep in the shells
+    regs.close()
+    lds.close()
+
+
+def test_paper_disk1k_trajectory_tracks_the_oracle():
+    """90 encounter steps of the paper's 1k benchmark disk (Sec. 3) on the
+    device against the oracle's own 90 steps (stored by
+    tests/golden/make_enc_paper_disk1k.py): every 10 steps the relative energy
+    error, the smallest separation and the number of flagged pairs agree.  The
+    two sides round differently from the first step on, so this checks that the
+    whole integrator (groups through the shells, evaluation, level-0
+    reweighting) follows the same trajectory over many steps, not only one step
+    from shared inputs."""
+    import json
+    import os
+    import torch
+    from paper_2304_07325_amd import binding as B
+    from tests.golden.make_enc_paper_disk1k import split_energy
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "enc_paper_disk1k.json")))
+    w = dg.WORKLOADS[gold["disk"]]
+    disk = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"])
+    s0 = disk.state(0)
+    n, n_m, h, f = gold["n"], gold["n_massive"], gold["h"], gold["rcrit_factor"]
+    e0, _ = split_energy(s0)
+    st = B.to_device_state(s0)
+    ctx = B.Context(max_n=n, max_pairs=1 << 14)
+    out = B.Outputs(n, 1 << 12)
+    G.say("paper disk1k, 90 encounter steps")
+    ctx.enc_prepare(st, n_m, h, f, out)
+    want = {c["step"]: c for c in gold["checkpoints"]}
+    for k in range(1, max(want) + 1):
+        ctx.step_enc(st, n_m, h, f, out)
+        if k in want:
+            torch.cuda.synchronize()
+            o = out.to_host()
+            s = {key: v.cpu().numpy() for key, v in st.items()}
+            e, rmin = split_energy(s)
+            err = abs(e - e0) / abs(e0)
+            c = want[k]
+            assert o["status"] == 0 and o["n_pairs"] == c["n_pairs"], (k, o["status"], o["n_pairs"], c)
+            # energy errors of 1e-11 .. 2e-9 of |E|: 5 % of the value plus the
+            # rounding of E itself (about 1e-12 of |E| over 500k pair terms)
+            assert abs(err - c["energy_rel_err"]) <= 0.05 * c["energy_rel_err"] + 1e-12, (k, err, c)
+            assert abs(rmin - c["min_separation"]) <= 1e-6 * c["min_separation"], (k, rmin, c)
+    ctx.close()
