@@ -82,9 +82,10 @@ extern "C" {
 #define SYMBA_OPT_ENC_FUSE 9    /* symba_step_enc / symba_enc_prepare on problems of at most 256 bodies:
                                    1 (default) = the work around the evaluation in two fused launches,
                                    0 = the general launches (the same results, bit for bit) */
-#define SYMBA_OPT_ENC_PAIR 10   /* symba_step_enc, encounter groups of one pair (two bodies): 1 (default) =
-                                   integrated through the shells with the two bodies in registers, 0 = by the
-                                   routines for groups of any size (the same results, bit for bit) */
+#define SYMBA_OPT_ENC_REGS 10   /* symba_step_enc, encounter groups of at most 64 bodies and 64 pairs:
+                                   1 (default) = integrated through the shells with bodies and pairs in
+                                   registers (lane per body, lane per pair), 0 = by the routines for groups of
+                                   any size, which keep them in LDS (the same results, bit for bit) */
 
 /* Values of SYMBA_OPT_ACC.  The paper's loop (Sec. 2) sums the pair
  * interactions, the kick term of the democratic heliocentric splitting

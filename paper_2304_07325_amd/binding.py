@@ -21,7 +21,7 @@ ENC_MAX_PAIRS, ENC_MAX_GROUP_PAIRS = 8192, 255
 FIELD_SEG_ROWS = 192   # massive rows per field task
 OPT_TILE_ROWS, OPT_FIELD_ROWS, OPT_SCREEN, OPT_TIMING, OPT_BIN, OPT_ACC, OPT_SPLIT = 1, 2, 4, 5, 6, 7, 8
 OPT_ENC_FUSE = 9
-OPT_ENC_PAIR = 10
+OPT_ENC_REGS = 10
 SCREEN_AUTO, SCREEN_FP32, SCREEN_FP64 = 0, 1, 2
 ACC_INTERACTION, ACC_HELIO = 0, 1
 

@@ -58,7 +58,7 @@ struct symba_ctx {
     int opt_rows = 0, opt_field_rows = 0, opt_screen = 0, opt_timing = 0, opt_bin = 0, opt_acc = 0;
     int opt_split = -1;  // split diagonals of the folded triangle, -1 = automatic
     int opt_enc_fuse = 1;  // fused encounter-step launches for one-block problems
-    int opt_enc_pair = 1;  // one-pair groups integrated in registers
+    int opt_enc_regs = 1;  // small encounter groups integrated in registers
     double *ind = nullptr;  // [max_n / kIndBodies + max_problems][3] indirect-term partial sums (SYMBA_ACC_HELIO)
     // tile rows chosen by symba_autotune per size class (floor(log2(n_tri))), 0 = not tuned
     int tuned_rows[64] = {};
@@ -469,9 +469,9 @@ int symba_set_option(symba_ctx *c, int option, int value) {
             if (value != 0 && value != 1) return SYMBA_EINVAL;
             c->opt_enc_fuse = value;
             return SYMBA_OK;
-        case SYMBA_OPT_ENC_PAIR:
+        case SYMBA_OPT_ENC_REGS:
             if (value != 0 && value != 1) return SYMBA_EINVAL;
-            c->opt_enc_pair = value;
+            c->opt_enc_regs = value;
             return SYMBA_OK;
         case SYMBA_OPT_ACC:
             if (value != SYMBA_ACC_INTERACTION && value != SYMBA_ACC_HELIO) return SYMBA_EINVAL;
@@ -692,7 +692,7 @@ symba::EncDesc enc_desc(symba_ctx *c, const symba_mstate *s, int64_t n, int64_t 
     e.pair_cap = out->pair_cap;
     e.gp = c->enc_gp; e.gstart = c->enc_gstart; e.gskip = c->enc_gskip; e.ctl = c->enc_ctl;
     e.ingroup = c->ingroup;
-    e.pair_regs = c->opt_enc_pair;
+    e.regs = c->opt_enc_regs;
     return e;
 }
 

@@ -663,15 +663,172 @@ __device__ void drift_pair(const EncDesc &e, int g) {
     }
 }
 
+// Lane-uniform reads of another lane's value (the lane index is uniform).
+__device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_dbl(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// A group of at most one wave's bodies and pairs, loaded by load_group, then
+// integrated like integrate() with lane b holding body b and lane t pair t in
+// registers: a kick evaluates every pair's force at once (lane t) and each
+// body adds its pairs' terms in the pairs' order; the test runs on every pair
+// at once; the drifts on every body at once.  The same operations on the same
+// values as the LDS routines, so the same bits.
+__device__ void integrate_small(const EncDesc &e, GroupLds &G) {
+#pragma clang fp contract(off)
+    const int l = lane(), nb = G.nb, np = G.np;
+    const bool isb = l < nb, isp = l < np;
+    double x = 0.0, y = 0.0, z = 0.0, vx = 0.0, vy = 0.0, vz = 0.0, m = 0.0;
+    if (isb) {
+        x = G.x[l]; y = G.y[l]; z = G.z[l];
+        vx = G.vx[l]; vy = G.vy[l]; vz = G.vz[l];
+        m = G.m[l];
+    }
+    int pa = 0, pb = 0, depth = 0;  // pair l's bodies and level (0: no pair in this lane)
+    double R[kEncMaxLevel + 2];
+#pragma unroll
+    for (int q = 0; q < kEncMaxLevel + 2; ++q) R[q] = 0.0;
+    if (isp) {
+        pa = G.pa[l];
+        pb = G.pb[l];
+        depth = 1;
+#pragma unroll
+        for (int q = 0; q < kEncMaxLevel + 2; ++q) R[q] = G.rk[q][l];
+    }
+    int bd = isb ? 1 : 0;  // body l's deepest level
+    const double h = e.h;
+    double cax = 0.0, cay = 0.0, caz = 0.0;
+    bool cany = false;
+    unsigned subs = 0;
+    int k = 1;
+    bool enter = true;
+    int cached = -1;
+    while (true) {
+        const double tau = ldexp(h, -2 * k);
+        double rm = R[0], rk = R[1], rp = R[2];
+#pragma unroll
+        for (int q = 2; q <= kEncMaxLevel; ++q)
+            if (k == q) {
+                rm = R[q - 1];
+                rk = R[q];
+                rp = R[q + 1];
+            }
+        // the pairs' positions, for the kick and the test
+        const double xi = __shfl(x, pa), yi = __shfl(y, pa), zi = __shfl(z, pa);
+        const double xj = __shfl(x, pb), yj = __shfl(y, pb), zj = __shfl(z, pb);
+        if (!(enter && cached == k)) {
+            // lane t: pair t's level-k factor g (flagged `zero` outside the band)
+            const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+            const bool act = depth >= k;
+            bool zero = true;
+            double gf = 0.0;
+            if (act) {
+                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+                const bool ordered = rp < rk && rk < rm;
+                zero = ordered && (r >= rm || (k < kEncMaxLevel && r <= rp));
+                if (!zero) gf = force_factor(k, r, rm, rk, rp) / (r * r * r);
+            }
+            const unsigned long long act_mask = __ballot(act), zero_mask = __ballot(act && zero);
+            // lane b: its pairs' terms in the pairs' order
+            cax = cay = caz = 0.0;
+            cany = false;
+            for (int t = 0; t < np; ++t) {
+                if (!((act_mask >> t) & 1ull)) continue;
+                const int ia = lane_int(pa, t), ib = lane_int(pb, t);
+                if (l != ia && l != ib) continue;
+                cany = true;
+                if ((zero_mask >> t) & 1ull) continue;
+                const double gt = lane_dbl(gf, t), dxt = lane_dbl(dx, t), dyt = lane_dbl(dy, t),
+                             dzt = lane_dbl(dz, t);
+                if (l == ia) {
+                    const double sgl = lane_dbl(m, ib) * gt;
+                    cax = __builtin_fma(sgl, dxt, cax);
+                    cay = __builtin_fma(sgl, dyt, cay);
+                    caz = __builtin_fma(sgl, dzt, caz);
+                } else {
+                    const double sgl = lane_dbl(m, ia) * gt;
+                    cax = __builtin_fma(-sgl, dxt, cax);
+                    cay = __builtin_fma(-sgl, dyt, cay);
+                    caz = __builtin_fma(-sgl, dzt, caz);
+                }
+            }
+        }
+        if (cany) {
+            const double dt = 0.5 * tau;
+            vx = __builtin_fma(dt, cax, vx);
+            vy = __builtin_fma(dt, cay, vy);
+            vz = __builtin_fma(dt, caz, vz);
+        }
+        if (enter) {
+            cached = -1;
+            bool deeper = false;
+            if (k < kEncMaxLevel) {
+                // the level-k test of every pair at level k or deeper
+                const double vxi = __shfl(vx, pa), vyi = __shfl(vy, pa), vzi = __shfl(vz, pa);
+                const double vxj = __shfl(vx, pb), vyj = __shfl(vy, pb), vzj = __shfl(vz, pb);
+                bool fl = false;
+                if (depth >= k) {
+                    fl = encounter(xj - xi, yj - yi, zj - zi, vxj - vxi, vyj - vyi, vzj - vzi, rk, tau);
+                    depth = fl ? k + 1 : k;
+                }
+                deeper = __ballot(fl) != 0;
+                // each body's deepest level
+                bd = 0;
+                for (int t = 0; t < np; ++t) {
+                    const int dt_ = lane_int(depth, t), ia = lane_int(pa, t), ib = lane_int(pb, t);
+                    if (l == ia || l == ib) bd = max(bd, dt_);
+                }
+            }
+            // the bodies whose deepest pair is at level k (at least k at the
+            // deepest level) drift for tau
+            if (isb && (k == kEncMaxLevel ? bd >= k : bd == k)) kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
+            if (deeper) {
+                ++k;
+                subs &= ~(3u << (2 * k));
+            } else {
+                enter = false;
+            }
+        } else {
+            cached = k;
+            const unsigned done = ((subs >> (2 * k)) & 3u) + 1u;
+            subs = (subs & ~(3u << (2 * k))) | ((done & 3u) << (2 * k));
+            if (done < (unsigned)kEncSub) {
+                enter = true;
+            } else if (k == 1) {
+                break;
+            } else {
+                --k;
+            }
+        }
+    }
+    if (isb) {
+        const int b = G.body[l];
+        e.x[b] = x;
+        e.y[b] = y;
+        e.z[b] = z;
+        e.vx[b] = vx;
+        e.vy[b] = vy;
+        e.vz[b] = vz;
+        e.ingroup[b] = 0;
+    }
+    wave_sync();
+}
+
 // One group's drift over the step, from its bodies in memory back to them
 // (the table marked them, so the drift kernels left them alone).  One wave.
 __device__ void drift_group(const EncDesc &e, GroupLds &G, int g) {
     if (e.gskip[g]) return;
-    if (e.pair_regs && e.gstart[g + 1] - e.gstart[g] == 1) {
+    if (e.regs && e.gstart[g + 1] - e.gstart[g] == 1) {
         drift_pair(e, g);
         return;
     }
     if (!load_group(e, G, g, true)) return;
+    if (e.regs && G.nb <= kGroupThreads && G.np <= kGroupThreads) {
+        integrate_small(e, G);
+        return;
+    }
     integrate(G, e.h);
     for (int b = lane(); b < G.nb; b += kGroupThreads) {
         const int k = G.body[b];

@@ -153,7 +153,7 @@ struct EncDesc {
     int32_t *ctl;     // [kEncCtlInts]
     int32_t *ingroup; // [n] 1 for bodies of resolved groups while the step runs, zero between calls
     int mark;         // 1: the table marks ingroup (the table at the step's start)
-    int pair_regs;    // 1: groups of one pair integrated with the two bodies in registers
+    int regs;         // 1: groups of at most one wave's bodies and pairs integrated in registers
 };
 
 // Encounter-step launches (csrc/symba_enc.hip) and the drifts of the

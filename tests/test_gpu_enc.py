@@ -422,14 +422,29 @@ def _binary(extra=0):
     return _state(x, v, [m] * (2 + extra))
 
 
-@pytest.mark.parametrize("case", ["flyby", "binary", "binary_wide", "disk1k"])
-def test_one_pair_groups_in_registers_are_bit_identical(case):
-    """Groups of one pair run with their two bodies in registers
-    (SYMBA_OPT_ENC_PAIR = 1); the routines for groups of any size
-    (SYMBA_OPT_ENC_PAIR = 0) give the same bits: a fast flyby, a tight binary
-    at the deepest level for the whole step (one block, and 300 bodies through
-    the general launches), and 20 steps of the paper's 1k disk (groups of one
-    pair and larger ones in the same launch)."""
+def _triple():
+    """The tight binary with a third body 1.5e-4 AU from its centre on a
+    circular orbit about it: a group of three pairs, all in the deepest shell."""
+    s = _binary()
+    m, a, d = 3e-8, 10.0, 1.5e-4
+    vc, v3 = math.sqrt(1.0 / a), math.sqrt(2 * m / d)
+    x = np.stack([s["x"], s["y"], s["z"]], 1).tolist() + [[a, d, 0.0]]
+    v = [[0.0, vc - math.sqrt(2 * m / 2e-5) / 2, 0.0], [0.0, vc + math.sqrt(2 * m / 2e-5) / 2, 0.0],
+         [-v3, vc, 0.0]]
+    return _state(x, v, [m, m, m])
+
+
+@pytest.mark.parametrize("case", ["flyby", "binary", "binary_wide", "triple", "cluster", "cluster_small", "disk1k"])
+def test_small_groups_in_registers_are_bit_identical(case):
+    """Groups of at most 64 bodies and 64 pairs run in registers (one pair:
+    the two bodies in two lanes; more: a lane per body and a lane per pair),
+    SYMBA_OPT_ENC_REGS = 1; the routines for groups of any size, which keep
+    them in LDS (SYMBA_OPT_ENC_REGS = 0), give the same bits: a fast flyby, a
+    tight binary at the deepest level for the whole step (one block, and 300
+    bodies through the general launches), a tight triple, a crowded cluster
+    (one group over the limit of the register path next to a smaller one), a
+    small cluster (one group of many pairs in registers) and 20 steps of the
+    paper's 1k disk."""
     from paper_2304_07325_amd import binding as B
     if case == "flyby":
         x, v, m = _flyby(sep=0.15)
@@ -438,17 +453,25 @@ def test_one_pair_groups_in_registers_are_bit_identical(case):
         s, n_m, h, steps = _binary(), 2, dg.DT_HALF_YEAR, 1
     elif case == "binary_wide":
         s, n_m, h, steps = _binary(298), 300, dg.DT_HALF_YEAR, 1
+    elif case == "triple":
+        s, n_m, h, steps = _triple(), 3, 0.05, 2
+    elif case == "cluster":
+        s, h, steps = _cluster(), 0.01, 4
+        n_m = 40
+    elif case == "cluster_small":
+        s, h, steps = _cluster(n=16, spread=0.05), 0.01, 4
+        n_m = 16
     else:
         w = dg.WORKLOADS["disk1k"]
         s = dg.make_disk(w["n"], w["n_massive"], w["kind"], w["seed"]).state(0)
         n_m, h, steps = w["n_massive"], dg.DT_HALF_YEAR, 20
     n = s["x"].size
     regs, lds = Dev(n), Dev(n)
-    lds.ctx.set_option(B.OPT_ENC_PAIR, 0)
+    lds.ctx.set_option(B.OPT_ENC_REGS, 0)
     for d in (regs, lds):
         d.load(s)
         d.ctx.enc_prepare(d.st, n_m, h, F, d.out)
-    G.say("one-pair groups in registers vs LDS,", case)
+    G.say("small groups in registers vs LDS,", case)
     for step in range(steps):
         for d in (regs, lds):
             d.ctx.step_enc(d.st, n_m, h, F, d.out)
