@@ -135,6 +135,7 @@ __device__ void build_table(const EncDesc &e, unsigned long long *key) {
     if ((st & kStatusCapacityBit) || np64 > e.pair_cap || np64 > kEncMaxPairs || np64 <= 0) {
         if (tid == 0) {
             e.ctl[kEncCtlGroups] = 0;
+            e.ctl[kEncCtlClaim] = 0;
             if (np64 > 0) e.ctl[kEncCtlSkipped] = 1;
         }
         return;
@@ -196,6 +197,7 @@ __device__ void build_table(const EncDesc &e, unsigned long long *key) {
     if (tid == 0) {
         e.gstart[total] = np;
         e.ctl[kEncCtlGroups] = total;
+        e.ctl[kEncCtlClaim] = 0;
     }
     __syncthreads();
     // groups over the limit are left out (and reported); the others' bodies
@@ -843,10 +845,20 @@ __device__ void drift_group(const EncDesc &e, GroupLds &G, int g) {
     wave_sync();
 }
 
+// Each workgroup takes the next group from a counter when it is free: a
+// group's cost varies by orders of magnitude (the depth of its recursion), so
+// a fixed deal could give two deep groups to one workgroup.  Groups are
+// independent, so which workgroup integrates which changes no bit.
 __global__ __launch_bounds__(kGroupThreads) void k_enc_groups(const EncDesc e) {
     __shared__ GroupLds G;
     const int ng = e.ctl[kEncCtlGroups];
-    for (int g = blockIdx.x; g < ng; g += gridDim.x) drift_group(e, G, g);
+    while (true) {
+        int g = 0;
+        if (lane() == 0) g = atomicAdd(e.ctl + kEncCtlClaim, 1);
+        g = __shfl(g, 0);
+        if (g >= ng) break;
+        drift_group(e, G, g);
+    }
 }
 
 __global__ __launch_bounds__(kGroupThreads) void k_enc_level0(const EncDesc e) {

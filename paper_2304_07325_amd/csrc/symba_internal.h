@@ -130,6 +130,7 @@ constexpr int kEncSub = 4;            // substeps per level
 constexpr double kEncShellRatio = 2.08;
 constexpr int kEncCtlGroups = 0;      // ctl[]: groups of the current table
 constexpr int kEncCtlSkipped = 1;     // ctl[]: nonzero when pairs went unresolved this step
+constexpr int kEncCtlClaim = 2;       // ctl[]: groups the group launch's workgroups have taken so far
 constexpr int kEncCtlInts = 4;
 
 struct EncDesc {
