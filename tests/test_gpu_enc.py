@@ -529,3 +529,42 @@ def test_paper_disk1k_trajectory_tracks_the_oracle():
             assert abs(err - c["energy_rel_err"]) <= 0.05 * c["energy_rel_err"] + 1e-12, (k, err, c)
             assert abs(rmin - c["min_separation"]) <= 1e-6 * c["min_separation"], (k, rmin, c)
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["binary", "triple"])
+def test_deepest_level_step_matches_the_oracle(case, ora):
+    """One step of a tight binary and of a tight triple that stay inside the
+    deepest shell for the whole step (every substep down to level 8: 87,380
+    for the binary, its short arcs drifted by the f and g series, its groups
+    in the register forms) against the oracle's step, stored by
+    tests/golden/make_enc_deep.py, from the oracle's own inputs.  Such a step
+    is ill-conditioned (the binary turns about 1,400 times), so each
+    coordinate is held to 30 times the spread that moving one input
+    coordinate by one ulp gives the oracle's own step (the device rounds
+    differently in every operation, not in one input: about ten times that
+    spread measured), plus the usual tolerance; the pairs must be the same."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "enc_deep.json")))["cases"][case]
+    s = {"binary": _binary, "triple": _triple}[case]()
+    n_m, h = gold["n_m"], gold["h"]
+    acc, pairs = E.prepare(s, n_m, h, F, ora=ora)
+    dev = Dev(s["x"].size)
+    G.say("deepest level, one step,", case)
+    dev.load(s, acc, pairs, ora)
+    dev.ctx.step_enc(dev.st, n_m, h, F, dev.out)
+    got = dev.state()
+    out = dev.out.to_host()
+    want = dict(s)
+    want.update({k: np.asarray(v, dtype=np.float64) for k, v in gold["state"].items()})
+    pscale = max(np.abs(want[k]).max() for k in ("x", "y", "z")) + 1.0
+    vscale = max(np.abs(want[k]).max() for k in ("vx", "vy", "vz"))
+    for k in KEYS:
+        scale = pscale if k in ("x", "y", "z") else vscale
+        tol = 30.0 * gold["spread"][k] + STATE_TOL * scale
+        assert np.abs(got[k] - want[k]).max() <= tol, (k, np.abs(got[k] - want[k]).max(), tol)
+    assert out["status"] == 0
+    assert np.array_equal(np.stack([out["pair_i"], out["pair_j"]], 1), np.asarray(gold["pairs"]).reshape(-1, 2))
+    scale = np.abs(ora.accel(want, n_m)).max()
+    assert np.abs(out["acc"] - np.asarray(gold["acc"])).max() <= 30.0 * gold["acc_spread"] + ACC_TOL * scale
+    dev.close()
