@@ -68,9 +68,21 @@ __device__ __forceinline__ void partition(double x, double &f, double &df) {
 }
 
 // F(r) and dF/dr of the changeover between the shells hi = R_k and lo =
-// R_{k+1} (F_k of the pair).
+// R_{k+1} (F_k of the pair).  At r <= lo the argument rounds to at most 0
+// and at r >= hi to at least 1, where the clipped f_3 gives exactly 0 and 0,
+// or 1 and 0: those values directly, without the divisions (same bits).
 __device__ __forceinline__ void changeover(double r, double hi, double lo, double &F, double &dF) {
 #pragma clang fp contract(off)
+    if (r <= lo) {
+        F = 0.0;
+        dF = 0.0;
+        return;
+    }
+    if (r >= hi) {
+        F = 1.0;
+        dF = 0.0;
+        return;
+    }
     const double w = hi - lo;
     double f, df;
     partition((r - lo) / w, f, df);
@@ -97,6 +109,19 @@ __device__ __forceinline__ double force_factor(int k, double r, double rm, doubl
         dw = dFa - dFb;
     }
     return __builtin_fma(-r, dw, w);
+}
+
+// A pair's separation r and 1/r^3 from r^2 inside the substeps' serial
+// chain: the reciprocal-square-root estimate corrected to second order in its
+// relative error e (truncation ~ (5/16) e^3, so a few ulp), without the
+// square root's and the division's longer sequences.
+__device__ __forceinline__ void pair_r(double r2, double &r, double &ir3) {
+#pragma clang fp contract(off)
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
+    const double ir = y0 * __builtin_fma(e, __builtin_fma(e, 0.375, 0.5), 1.0);
+    r = r2 * ir;
+    ir3 = ir * ir * ir;
 }
 
 // The close-encounter test with radius `radius` over an interval tau (for tau
@@ -382,11 +407,12 @@ __device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
                 if (i != b && j != b) continue;
                 any = true;
                 const double dx = G.x[j] - G.x[i], dy = G.y[j] - G.y[i], dz = G.z[j] - G.z[i];
-                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+                double r, ir3;
+                pair_r(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)), r, ir3);
                 const double rm = G.rk[k - 1][t], rk = G.rk[k][t], rp = G.rk[k + 1][t];
                 const bool ordered = rp < rk && rk < rm;
                 if (ordered && (r >= rm || (k < kEncMaxLevel && r <= rp))) continue;
-                const double g = force_factor(k, r, rm, rk, rp) / (r * r * r);
+                const double g = force_factor(k, r, rm, rk, rp) * ir3;
                 if (b == i) {
                     const double s = G.m[j] * g;
                     ax = __builtin_fma(s, dx, ax);
@@ -597,10 +623,11 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                 const double xo = swap_pair(x), yo = swap_pair(y), zo = swap_pair(z);
                 const double dx = first ? xo - x : x - xo, dy = first ? yo - y : y - yo,
                              dz = first ? zo - z : z - zo;
-                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+                double r, ir3;
+                pair_r(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)), r, ir3);
                 const bool ordered = rp < rk && rk < rm;
                 if (!(ordered && (r >= rm || (k < kEncMaxLevel && r <= rp)))) {
-                    const double gf = force_factor(k, r, rm, rk, rp) / (r * r * r);
+                    const double gf = force_factor(k, r, rm, rk, rp) * ir3;
                     const double s = m_other * gf;
                     if (first) {
                         cax = __builtin_fma(s, dx, cax);
@@ -727,10 +754,11 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
             bool zero = true;
             double gf = 0.0;
             if (act) {
-                const double r = sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+                double r, ir3;
+                pair_r(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)), r, ir3);
                 const bool ordered = rp < rk && rk < rm;
                 zero = ordered && (r >= rm || (k < kEncMaxLevel && r <= rp));
-                if (!zero) gf = force_factor(k, r, rm, rk, rp) / (r * r * r);
+                if (!zero) gf = force_factor(k, r, rm, rk, rp) * ir3;
             }
             const unsigned long long act_mask = __ballot(act), zero_mask = __ballot(act && zero);
             // lane b: its pairs' terms in the pairs' order
