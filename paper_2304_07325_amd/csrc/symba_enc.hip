@@ -564,6 +564,16 @@ __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
     wave_sync();
 }
 
+// R[i] of a register array for a wave-uniform i in [0, L + 1] (selects over
+// constant indices, so the array stays in registers).
+__device__ __forceinline__ double shell_at(const double (&R)[kEncMaxLevel + 2], int i) {
+    double v = R[0];
+#pragma unroll
+    for (int q = 1; q < kEncMaxLevel + 2; ++q)
+        if (i == q) v = R[q];
+    return v;
+}
+
 // The value of lane l ^ 1 (DPP quad_perm [1, 0, 3, 2]: lanes 0 and 1 swap).
 __device__ __forceinline__ double swap_pair(double v) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0xb1, 0xf, 0xf, true);
@@ -603,16 +613,9 @@ __device__ void drift_pair(const EncDesc &e, int g) {
     int k = 1;
     bool enter = true;
     int cached = -1;
+    double rm = R[0], rk = R[1], rp = R[2];  // R_{k-1}, R_k, R_{k+1}, moved along with k
     while (true) {
         const double tau = ldexp(h, -2 * k);
-        double rm = R[0], rk = R[1], rp = R[2];  // R_{k-1}, R_k, R_{k+1}
-#pragma unroll
-        for (int q = 2; q <= kEncMaxLevel; ++q)
-            if (k == q) {
-                rm = R[q - 1];
-                rk = R[q];
-                rp = R[q + 1];
-            }
         // kick of level k for tau / 2 (the pair's force at level k, nothing
         // below it), the accelerations of the last kick again when no body
         // has drifted since it at this level
@@ -663,6 +666,9 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                 if (depth > k) {
                     ++k;
                     subs &= ~(3u << (2 * k));
+                    rm = rk;
+                    rk = rp;
+                    rp = shell_at(R, k + 1);
                 } else {
                     kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
                     enter = false;
@@ -678,6 +684,9 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                 break;
             } else {
                 --k;
+                rp = rk;
+                rk = rm;
+                rm = shell_at(R, k - 1);
             }
         }
     }
@@ -734,16 +743,9 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
     int k = 1;
     bool enter = true;
     int cached = -1;
+    double rm = R[0], rk = R[1], rp = R[2];  // pair lane's R_{k-1}, R_k, R_{k+1}, moved along with k
     while (true) {
         const double tau = ldexp(h, -2 * k);
-        double rm = R[0], rk = R[1], rp = R[2];
-#pragma unroll
-        for (int q = 2; q <= kEncMaxLevel; ++q)
-            if (k == q) {
-                rm = R[q - 1];
-                rk = R[q];
-                rp = R[q + 1];
-            }
         // the pairs' positions, for the kick and the test
         const double xi = __shfl(x, pa), yi = __shfl(y, pa), zi = __shfl(z, pa);
         const double xj = __shfl(x, pb), yj = __shfl(y, pb), zj = __shfl(z, pb);
@@ -817,6 +819,9 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
             if (deeper) {
                 ++k;
                 subs &= ~(3u << (2 * k));
+                rm = rk;
+                rk = rp;
+                rp = shell_at(R, k + 1);
             } else {
                 enter = false;
             }
@@ -830,6 +835,9 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 break;
             } else {
                 --k;
+                rp = rk;
+                rk = rm;
+                rm = shell_at(R, k - 1);
             }
         }
     }
