@@ -623,24 +623,20 @@ __device__ void drift_pair(const EncDesc &e, int g) {
             cax = cay = caz = 0.0;
             cany = depth >= k;
             if (cany) {
-                const double xo = swap_pair(x), yo = swap_pair(y), zo = swap_pair(z);
-                const double dx = first ? xo - x : x - xo, dy = first ? yo - y : y - yo,
-                             dz = first ? zo - z : z - zo;
+                // the partner's position minus this lane's: x_j - x_i on
+                // body i, and on body j its exact negative, so the squares
+                // are those of x_j - x_i and s (x_i - x_j) = -s (x_j - x_i)
+                // gives body j's term without a branch
+                const double dx = swap_pair(x) - x, dy = swap_pair(y) - y, dz = swap_pair(z) - z;
                 double r, ir3;
                 pair_r(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)), r, ir3);
                 const bool ordered = rp < rk && rk < rm;
                 if (!(ordered && (r >= rm || (k < kEncMaxLevel && r <= rp)))) {
                     const double gf = force_factor(k, r, rm, rk, rp) * ir3;
                     const double s = m_other * gf;
-                    if (first) {
-                        cax = __builtin_fma(s, dx, cax);
-                        cay = __builtin_fma(s, dy, cay);
-                        caz = __builtin_fma(s, dz, caz);
-                    } else {
-                        cax = __builtin_fma(-s, dx, cax);
-                        cay = __builtin_fma(-s, dy, cay);
-                        caz = __builtin_fma(-s, dz, caz);
-                    }
+                    cax = __builtin_fma(s, dx, cax);
+                    cay = __builtin_fma(s, dy, cay);
+                    caz = __builtin_fma(s, dz, caz);
                 }
             }
         }
@@ -658,10 +654,10 @@ __device__ void drift_pair(const EncDesc &e, int g) {
             } else {
                 // the level-k test over tau: the pair goes to level k + 1 or
                 // stays at k; every lane tests the same values, lane 0 decides
-                const double xo = swap_pair(x), yo = swap_pair(y), zo = swap_pair(z);
-                const double vxo = swap_pair(vx), vyo = swap_pair(vy), vzo = swap_pair(vz);
-                const bool fl = first ? encounter(xo - x, yo - y, zo - z, vxo - vx, vyo - vy, vzo - vz, rk, tau)
-                                      : encounter(x - xo, y - yo, z - zo, vx - vxo, vy - vyo, vz - vzo, rk, tau);
+                // on body j both differences are the exact negatives of body
+                // i's, which the test's products do not see
+                const bool fl = encounter(swap_pair(x) - x, swap_pair(y) - y, swap_pair(z) - z, swap_pair(vx) - vx,
+                                          swap_pair(vy) - vy, swap_pair(vz) - vz, rk, tau);
                 depth = __builtin_amdgcn_readfirstlane(fl ? k + 1 : k);
                 if (depth > k) {
                     ++k;
