@@ -742,12 +742,16 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
     double rm = R[0], rk = R[1], rp = R[2];  // pair lane's R_{k-1}, R_k, R_{k+1}, moved along with k
     while (true) {
         const double tau = ldexp(h, -2 * k);
-        // the pairs' positions, for the kick and the test
-        const double xi = __shfl(x, pa), yi = __shfl(y, pa), zi = __shfl(z, pa);
-        const double xj = __shfl(x, pb), yj = __shfl(y, pb), zj = __shfl(z, pb);
-        if (!(enter && cached == k)) {
+        const bool reuse = enter && cached == k;
+        // lane t: pair t's x_j - x_i, for a new kick and for the test
+        double dx = 0.0, dy = 0.0, dz = 0.0;
+        if (!reuse || (enter && k < kEncMaxLevel)) {
+            dx = __shfl(x, pb) - __shfl(x, pa);
+            dy = __shfl(y, pb) - __shfl(y, pa);
+            dz = __shfl(z, pb) - __shfl(z, pa);
+        }
+        if (!reuse) {
             // lane t: pair t's level-k factor g (flagged `zero` outside the band)
-            const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
             const bool act = depth >= k;
             bool zero = true;
             double gf = 0.0;
@@ -770,17 +774,11 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 if ((zero_mask >> t) & 1ull) continue;
                 const double gt = lane_dbl(gf, t), dxt = lane_dbl(dx, t), dyt = lane_dbl(dy, t),
                              dzt = lane_dbl(dz, t);
-                if (l == ia) {
-                    const double sgl = lane_dbl(m, ib) * gt;
-                    cax = __builtin_fma(sgl, dxt, cax);
-                    cay = __builtin_fma(sgl, dyt, cay);
-                    caz = __builtin_fma(sgl, dzt, caz);
-                } else {
-                    const double sgl = lane_dbl(m, ia) * gt;
-                    cax = __builtin_fma(-sgl, dxt, cax);
-                    cay = __builtin_fma(-sgl, dyt, cay);
-                    caz = __builtin_fma(-sgl, dzt, caz);
-                }
+                // body i adds m_j g (x_j - x_i), body j adds -m_i g (x_j - x_i)
+                const double sgl = l == ia ? lane_dbl(m, ib) * gt : -(lane_dbl(m, ia) * gt);
+                cax = __builtin_fma(sgl, dxt, cax);
+                cay = __builtin_fma(sgl, dyt, cay);
+                caz = __builtin_fma(sgl, dzt, caz);
             }
         }
         if (cany) {
@@ -794,11 +792,11 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
             bool deeper = false;
             if (k < kEncMaxLevel) {
                 // the level-k test of every pair at level k or deeper
-                const double vxi = __shfl(vx, pa), vyi = __shfl(vy, pa), vzi = __shfl(vz, pa);
-                const double vxj = __shfl(vx, pb), vyj = __shfl(vy, pb), vzj = __shfl(vz, pb);
+                const double dvx = __shfl(vx, pb) - __shfl(vx, pa), dvy = __shfl(vy, pb) - __shfl(vy, pa),
+                             dvz = __shfl(vz, pb) - __shfl(vz, pa);
                 bool fl = false;
                 if (depth >= k) {
-                    fl = encounter(xj - xi, yj - yi, zj - zi, vxj - vxi, vyj - vyi, vzj - vzi, rk, tau);
+                    fl = encounter(dx, dy, dz, dvx, dvy, dvz, rk, tau);
                     depth = fl ? k + 1 : k;
                 }
                 deeper = __ballot(fl) != 0;
