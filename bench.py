@@ -470,7 +470,8 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
 
     def invariants(s):
         """Energy of the split Hamiltonian (Kepler + Sun + interaction terms,
-        heliocentric positions, barycentric velocities) and angular momentum."""
+        heliocentric positions, barycentric velocities), angular momentum and
+        the smallest pair separation."""
         x = np.stack([s["x"], s["y"], s["z"]], 1)
         v = np.stack([s["vx"], s["vy"], s["vz"]], 1)
         m = s["m"]
@@ -481,7 +482,7 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
         iu = np.triu_indices(len(m), 1)
         e -= float(np.sum((m[:, None] * m[None, :])[iu] / r[iu]))
         L = (m[:, None] * np.cross(x, v)).sum(0)
-        return e, L
+        return e, L, float(r[iu].min())
 
     # eager steps on a copy, for the launch cost the graphs below remove
     chunks = 50
@@ -516,33 +517,47 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
         for _ in range(graph_steps):
             step(st, ctx, out, stream=side)
     torch.cuda.synchronize()
-    e0, L0 = invariants(s0)
+    e0, L0, _ = invariants(s0)
     worst_e, worst_l, skipped = 0.0, 0.0, 0
-    t0 = time.perf_counter()
-    done, first_rate = 0, None
+    # the invariants after every graph of steps (outside the timed time): an
+    # approach closer than the deepest shell resolves (a collision, which the
+    # paper's code would merge) shows as a jump of the energy error
+    jump_at, worst_before, rmin = None, 0.0, float("inf")
+    wall, done, first_rate = 0.0, 0, None
     while done < total:
-        k = min(per, total - done)
-        for _ in range(k // graph_steps):
+        k = min(graph_steps, total - done)
+        t0 = time.perf_counter()
+        if k == graph_steps:
             graph.replay()
-        for _ in range(k % graph_steps):
-            step(st, ctx, out)
-        done += k
+        else:
+            for _ in range(k):
+                step(st, ctx, out)
         torch.cuda.synchronize()
-        if first_rate is None:
+        wall += time.perf_counter() - t0
+        done += k
+        if first_rate is None and done >= per:
             # the same steps as the eager timing above (the cost of a step
             # depends on how deep its encounters go, which changes over the run)
-            first_rate = done / (time.perf_counter() - t0)
+            first_rate = done / wall
         cur = {key: v.cpu().numpy() for key, v in st.items()}
-        e, L = invariants(cur)
-        worst_e = max(worst_e, abs(e - e0) / abs(e0))
+        e, L, rm = invariants(cur)
+        err = abs(e - e0) / abs(e0)
+        if jump_at is None and err > 1e-6:
+            jump_at = done
+        if jump_at is None:
+            worst_before = max(worst_before, err)
+        rmin = min(rmin, rm)
+        worst_e = max(worst_e, err)
         worst_l = max(worst_l, float(np.linalg.norm(L - L0) / np.linalg.norm(L0)))
-        skipped += bool(out.to_host()["status"] & B.STATUS_ENC_SKIPPED)
-    wall = time.perf_counter() - t0
+        skipped += bool(int(out.scalars32[1].item()) & B.STATUS_ENC_SKIPPED)
     _, flagged, calls = ctx.read_stats()
     r = {"n": 100, "step_years": h / dg.YEAR, "years": done * h / dg.YEAR, "steps": done,
          "stepper": "symba_step_enc" if encounters else "symba_step",
          "energy_rel_err_max": worst_e, "energy_rel_err_end": abs(e - e0) / abs(e0),
-         "angmom_rel_err_max": worst_l, "checkpoints": chunks,
+         "angmom_rel_err_max": worst_l, "checkpoints": -(-total // graph_steps), "checkpoint_steps": graph_steps,
+         "first_energy_jump_above_1e-6": None if jump_at is None else
+         {"by_step": jump_at, "years": jump_at * h / dg.YEAR, "energy_rel_err_max_before": worst_before},
+         "closest_sampled_separation_au": rmin,
          "encounter_pairs_per_step": flagged / max(calls, 1), "wall_s": wall,
          "steps_per_s": done / wall, "graph_steps": graph_steps,
          "first_steps": {"steps": per, "graph_steps_per_s": first_rate, "eager_steps_per_s": eager_rate}}
@@ -551,7 +566,9 @@ def accuracy_run(args, B, dg, torch, acc_disk, encounters):
     log(f"accuracy disk, {label}: {done} steps ({done * h / dg.YEAR:.0f} yr) in {wall:.1f} s ({done / wall:.0f} "
         f"steps/s in graphs of {graph_steps}; first {per} steps {first_rate:.0f} steps/s in graphs, "
         f"{eager_rate:.0f} eager), energy err max "
-        f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}")
+        f"{worst_e:.2e}, angular momentum err max {worst_l:.2e}" +
+        ("" if jump_at is None else f"; energy error first above 1e-6 by step {jump_at} "
+         f"({jump_at * h / dg.YEAR:.0f} yr), at most {worst_before:.2e} before"))
     ctx.close()
     return r
 
