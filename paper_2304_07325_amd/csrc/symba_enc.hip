@@ -653,9 +653,10 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                 enter = false;
             } else {
                 // the level-k test over tau: the pair goes to level k + 1 or
-                // stays at k; every lane tests the same values, lane 0 decides
-                // on body j both differences are the exact negatives of body
-                // i's, which the test's products do not see
+                // stays at k.  On body j both differences are the exact
+                // negatives of body i's, which the test's products do not
+                // see, so every lane decides the same; lane 0's decision is
+                // taken for the wave
                 const bool fl = encounter(swap_pair(x) - x, swap_pair(y) - y, swap_pair(z) - z, swap_pair(vx) - vx,
                                           swap_pair(vy) - vy, swap_pair(vz) - vz, rk, tau);
                 depth = __builtin_amdgcn_readfirstlane(fl ? k + 1 : k);
