@@ -564,14 +564,11 @@ __device__ void level0_group(const EncDesc &e, GroupLds &G, int g) {
     wave_sync();
 }
 
-// R[i] of a register array for a wave-uniform i in [0, L + 1] (selects over
-// constant indices, so the array stays in registers).
-__device__ __forceinline__ double shell_at(const double (&R)[kEncMaxLevel + 2], int i) {
-    double v = R[0];
-#pragma unroll
-    for (int q = 1; q < kEncMaxLevel + 2; ++q)
-        if (i == q) v = R[q];
-    return v;
+// Lane-uniform reads of another lane's value (the lane index is uniform).
+__device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_dbl(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
 // The value of lane l ^ 1 (DPP quad_perm [1, 0, 3, 2]: lanes 0 and 1 swap).
@@ -594,15 +591,22 @@ __device__ void drift_pair(const EncDesc &e, int g) {
     const int b = first ? e.pair_i[p] : e.pair_j[p];
     double x = e.x[b], y = e.y[b], z = e.z[b], vx = e.vx[b], vy = e.vy[b], vz = e.vz[b];
     const double m_other = swap_pair(b < e.n_tri ? e.m[b] : 0.0);
-    double R[kEncMaxLevel + 2];  // the pair's shells, as load_group computes them
+    // the pair's shells, as load_group computes them: R_0 = rc_i + rc_j of
+    // the rounded products, R_q = R_{q-1} / ratio.  Lane q keeps R_q (a
+    // register array indexed by the level would live in scratch memory);
+    // going one level deeper divides again, which gives the same bits
+    double Rl = 0.0, rm, rk, rp;  // R_{k-1}, R_k, R_{k+1}, moved along with k
     {
-        const double rc = e.f * e.rh[b];  // rc_i + rc_j of the rounded products, as load_group adds them
+        const double rc = e.f * e.rh[b];
         const double rc_other = swap_pair(rc);
         double r = first ? rc + rc_other : rc_other + rc;
+        rm = rk = rp = r;
 #pragma unroll
         for (int q = 0; q < kEncMaxLevel + 2; ++q) {
             if (q > 0) r = r / kEncShellRatio;
-            R[q] = r;
+            if (lane() == q) Rl = r;
+            if (q == 1) rk = r;
+            if (q == 2) rp = r;
         }
     }
     const double h = e.h;
@@ -613,7 +617,6 @@ __device__ void drift_pair(const EncDesc &e, int g) {
     int k = 1;
     bool enter = true;
     int cached = -1;
-    double rm = R[0], rk = R[1], rp = R[2];  // R_{k-1}, R_k, R_{k+1}, moved along with k
     while (true) {
         const double tau = ldexp(h, -2 * k);
         // kick of level k for tau / 2 (the pair's force at level k, nothing
@@ -665,7 +668,7 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                     subs &= ~(3u << (2 * k));
                     rm = rk;
                     rk = rp;
-                    rp = shell_at(R, k + 1);
+                    rp = rk / kEncShellRatio;
                 } else {
                     kepler::kepler_drift(x, y, z, vx, vy, vz, tau);
                     enter = false;
@@ -683,7 +686,7 @@ __device__ void drift_pair(const EncDesc &e, int g) {
                 --k;
                 rp = rk;
                 rk = rm;
-                rm = shell_at(R, k - 1);
+                rm = lane_dbl(Rl, k - 1);
             }
         }
     }
@@ -698,17 +701,11 @@ __device__ void drift_pair(const EncDesc &e, int g) {
     }
 }
 
-// Lane-uniform reads of another lane's value (the lane index is uniform).
-__device__ __forceinline__ int lane_int(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ double lane_dbl(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
 // A group of at most one wave's bodies and pairs, loaded by load_group, then
 // integrated like integrate() with lane b holding body b and lane t pair t in
 // registers: a kick evaluates every pair's force at once (lane t) and each
-// body adds its pairs' terms in the pairs' order; the test runs on every pair
+// body adds its pairs' terms in the pairs' order, fetching each from its
+// pair's lane (a walk over the body's own pairs); the test runs on every pair
 // at once; the drifts on every body at once.  The same operations on the same
 // values as the LDS routines, so the same bits.
 __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
@@ -722,17 +719,28 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
         m = G.m[l];
     }
     int pa = 0, pb = 0, depth = 0;  // pair l's bodies and level (0: no pair in this lane)
-    double R[kEncMaxLevel + 2];
-#pragma unroll
-    for (int q = 0; q < kEncMaxLevel + 2; ++q) R[q] = 0.0;
+    // pair lane's R_{k-1}, R_k, R_{k+1}, moved along with k: one level deeper
+    // divides again (how load_group made them, so the same bits), one level
+    // up reads the shell back from LDS
+    double rm = 0.0, rk = 0.0, rp = 0.0;
     if (isp) {
         pa = G.pa[l];
         pb = G.pb[l];
         depth = 1;
-#pragma unroll
-        for (int q = 0; q < kEncMaxLevel + 2; ++q) R[q] = G.rk[q][l];
+        rm = G.rk[0][l];
+        rk = G.rk[1][l];
+        rp = G.rk[2][l];
     }
     int bd = isb ? 1 : 0;  // body l's deepest level
+    // body l's pairs (bit t: pair t), those where it is body i, and on pair
+    // lane t the masses of its bodies, all fixed for the step
+    unsigned long long mine = 0ull, firstm = 0ull;
+    for (int t = 0; t < np; ++t) {
+        const int ia = lane_int(pa, t), ib = lane_int(pb, t);
+        if (l == ia) firstm |= 1ull << t;
+        if (l == ia || l == ib) mine |= 1ull << t;
+    }
+    const double ma = __shfl(m, pa), mb = __shfl(m, pb);
     const double h = e.h;
     double cax = 0.0, cay = 0.0, caz = 0.0;
     bool cany = false;
@@ -740,7 +748,6 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
     int k = 1;
     bool enter = true;
     int cached = -1;
-    double rm = R[0], rk = R[1], rp = R[2];  // pair lane's R_{k-1}, R_k, R_{k+1}, moved along with k
     while (true) {
         const double tau = ldexp(h, -2 * k);
         const bool reuse = enter && cached == k;
@@ -764,22 +771,27 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 if (!zero) gf = force_factor(k, r, rm, rk, rp) * ir3;
             }
             const unsigned long long act_mask = __ballot(act), zero_mask = __ballot(act && zero);
-            // lane b: its pairs' terms in the pairs' order
+            // body i adds m_j g (x_j - x_i), body j adds -m_i g (x_j - x_i)
+            const double si = mb * gf, sj = -(ma * gf);
+            // lane b: its nonzero level-k terms in the pairs' order, each
+            // fetched from its pair's lane (every lane takes part in the
+            // fetches; a lane with no term left fetches from itself)
             cax = cay = caz = 0.0;
-            cany = false;
-            for (int t = 0; t < np; ++t) {
-                if (!((act_mask >> t) & 1ull)) continue;
-                const int ia = lane_int(pa, t), ib = lane_int(pb, t);
-                if (l != ia && l != ib) continue;
-                cany = true;
-                if ((zero_mask >> t) & 1ull) continue;
-                const double gt = lane_dbl(gf, t), dxt = lane_dbl(dx, t), dyt = lane_dbl(dy, t),
-                             dzt = lane_dbl(dz, t);
-                // body i adds m_j g (x_j - x_i), body j adds -m_i g (x_j - x_i)
-                const double sgl = l == ia ? lane_dbl(m, ib) * gt : -(lane_dbl(m, ia) * gt);
-                cax = __builtin_fma(sgl, dxt, cax);
-                cay = __builtin_fma(sgl, dyt, cay);
-                caz = __builtin_fma(sgl, dzt, caz);
+            unsigned long long rest = mine & act_mask;
+            cany = rest != 0ull;
+            rest &= ~zero_mask;
+            while (__ballot(rest != 0ull)) {
+                const bool have = rest != 0ull;
+                const int t = have ? __builtin_ctzll(rest) : l;
+                rest &= rest - 1ull;
+                const double dxt = __shfl(dx, t), dyt = __shfl(dy, t), dzt = __shfl(dz, t);
+                const double sit = __shfl(si, t), sjt = __shfl(sj, t);
+                const double sgl = (firstm >> t) & 1ull ? sit : sjt;
+                if (have) {
+                    cax = __builtin_fma(sgl, dxt, cax);
+                    cay = __builtin_fma(sgl, dyt, cay);
+                    caz = __builtin_fma(sgl, dzt, caz);
+                }
             }
         }
         if (cany) {
@@ -801,11 +813,15 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                     depth = fl ? k + 1 : k;
                 }
                 deeper = __ballot(fl) != 0;
-                // each body's deepest level
+                // each body's deepest level, over its pairs
                 bd = 0;
-                for (int t = 0; t < np; ++t) {
-                    const int dt_ = lane_int(depth, t), ia = lane_int(pa, t), ib = lane_int(pb, t);
-                    if (l == ia || l == ib) bd = max(bd, dt_);
+                unsigned long long rest = mine;
+                while (__ballot(rest != 0ull)) {
+                    const bool have = rest != 0ull;
+                    const int t = have ? __builtin_ctzll(rest) : l;
+                    rest &= rest - 1ull;
+                    const int dt_ = __shfl(depth, t);
+                    if (have) bd = max(bd, dt_);
                 }
             }
             // the bodies whose deepest pair is at level k (at least k at the
@@ -816,7 +832,7 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 subs &= ~(3u << (2 * k));
                 rm = rk;
                 rk = rp;
-                rp = shell_at(R, k + 1);
+                rp = rk / kEncShellRatio;
             } else {
                 enter = false;
             }
@@ -832,7 +848,7 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 --k;
                 rp = rk;
                 rk = rm;
-                rm = shell_at(R, k - 1);
+                rm = G.rk[k - 1][l];
             }
         }
     }
