@@ -583,8 +583,10 @@ __device__ __forceinline__ double swap_pair(double v) {
 // body j in the odd ones (every lane pair holds the same two), each lane
 // reading its partner through a lane swap instead of LDS.  The same
 // operations on the same values as the LDS routines (kick, check, drift with
-// a single pair), so the same bits.
-__device__ void drift_pair(const EncDesc &e, int g) {
+// a single pair), so the same bits.  Not inlined: this form and the
+// small-group one each get their own register allocation and schedule
+// (inlined together, a change to one moved the other's substep time).
+__device__ __noinline__ void drift_pair(const EncDesc &e, int g) {
 #pragma clang fp contract(off)
     const int p = e.gp[e.gstart[g]];
     const bool first = (lane() & 1) == 0;
@@ -706,9 +708,11 @@ __device__ void drift_pair(const EncDesc &e, int g) {
 // registers: a kick evaluates every pair's force at once (lane t) and each
 // body adds its pairs' terms in the pairs' order, fetching each from its
 // pair's lane (a walk over the body's own pairs); the test runs on every pair
-// at once; the drifts on every body at once.  The same operations on the same
-// values as the LDS routines, so the same bits.
-__device__ void integrate_small(const EncDesc &e, GroupLds &G) {
+// at once; the drifts on every body at once.  While a single pair is at the
+// current level or deeper, its two bodies are read with lane-uniform reads
+// and only they can change level.  The same operations on the same values as
+// the LDS routines, so the same bits.  Not inlined, like drift_pair.
+__device__ __noinline__ void integrate_small(const EncDesc &e, GroupLds &G) {
 #pragma clang fp contract(off)
     const int l = lane(), nb = G.nb, np = G.np;
     const bool isb = l < nb, isp = l < np;
@@ -751,12 +755,32 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
     while (true) {
         const double tau = ldexp(h, -2 * k);
         const bool reuse = enter && cached == k;
-        // lane t: pair t's x_j - x_i, for a new kick and for the test
+        // the pairs at level k or deeper.  With one of them (the common case
+        // deep in a recursion, the group's other pairs waiting at shallower
+        // levels) its bodies ia1 and ib1 are read with lane-uniform reads
+        // instead of the fetches over the whole group; same values, so the
+        // same bits
+        const unsigned long long act_mask = __ballot(depth >= k);
+        const bool one = __popcll(act_mask) == 1;
+        int t1 = 0, ia1 = 0, ib1 = 0;
+        if (one) {
+            t1 = __builtin_ctzll(act_mask);
+            ia1 = lane_int(pa, t1);
+            ib1 = lane_int(pb, t1);
+        }
+        // lane t: pair t's x_j - x_i, for a new kick and for the test (with
+        // one pair at level k or deeper, every lane holds that pair's)
         double dx = 0.0, dy = 0.0, dz = 0.0;
         if (!reuse || (enter && k < kEncMaxLevel)) {
-            dx = __shfl(x, pb) - __shfl(x, pa);
-            dy = __shfl(y, pb) - __shfl(y, pa);
-            dz = __shfl(z, pb) - __shfl(z, pa);
+            if (one) {
+                dx = lane_dbl(x, ib1) - lane_dbl(x, ia1);
+                dy = lane_dbl(y, ib1) - lane_dbl(y, ia1);
+                dz = lane_dbl(z, ib1) - lane_dbl(z, ia1);
+            } else {
+                dx = __shfl(x, pb) - __shfl(x, pa);
+                dy = __shfl(y, pb) - __shfl(y, pa);
+                dz = __shfl(z, pb) - __shfl(z, pa);
+            }
         }
         if (!reuse) {
             // lane t: pair t's level-k factor g (flagged `zero` outside the band)
@@ -770,16 +794,26 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
                 zero = ordered && (r >= rm || (k < kEncMaxLevel && r <= rp));
                 if (!zero) gf = force_factor(k, r, rm, rk, rp) * ir3;
             }
-            const unsigned long long act_mask = __ballot(act), zero_mask = __ballot(act && zero);
+            const unsigned long long zero_mask = __ballot(act && zero);
             // body i adds m_j g (x_j - x_i), body j adds -m_i g (x_j - x_i)
             const double si = mb * gf, sj = -(ma * gf);
-            // lane b: its nonzero level-k terms in the pairs' order, each
-            // fetched from its pair's lane (every lane takes part in the
-            // fetches; a lane with no term left fetches from itself)
             cax = cay = caz = 0.0;
             unsigned long long rest = mine & act_mask;
             cany = rest != 0ull;
             rest &= ~zero_mask;
+            if (one) {
+                // the single term of bodies ia1 and ib1, from lane t1
+                const double sgl = l == ia1 ? lane_dbl(si, t1) : lane_dbl(sj, t1);
+                if (rest != 0ull) {
+                    cax = __builtin_fma(sgl, dx, cax);
+                    cay = __builtin_fma(sgl, dy, cay);
+                    caz = __builtin_fma(sgl, dz, caz);
+                }
+                rest = 0ull;
+            }
+            // lane b: its nonzero level-k terms in the pairs' order, each
+            // fetched from its pair's lane (every lane takes part in the
+            // fetches; a lane with no term left fetches from itself)
             while (__ballot(rest != 0ull)) {
                 const bool have = rest != 0ull;
                 const int t = have ? __builtin_ctzll(rest) : l;
@@ -805,17 +839,32 @@ __device__ void integrate_small(const EncDesc &e, GroupLds &G) {
             bool deeper = false;
             if (k < kEncMaxLevel) {
                 // the level-k test of every pair at level k or deeper
-                const double dvx = __shfl(vx, pb) - __shfl(vx, pa), dvy = __shfl(vy, pb) - __shfl(vy, pa),
-                             dvz = __shfl(vz, pb) - __shfl(vz, pa);
+                double dvx, dvy, dvz;
+                if (one) {
+                    dvx = lane_dbl(vx, ib1) - lane_dbl(vx, ia1);
+                    dvy = lane_dbl(vy, ib1) - lane_dbl(vy, ia1);
+                    dvz = lane_dbl(vz, ib1) - lane_dbl(vz, ia1);
+                } else {
+                    dvx = __shfl(vx, pb) - __shfl(vx, pa);
+                    dvy = __shfl(vy, pb) - __shfl(vy, pa);
+                    dvz = __shfl(vz, pb) - __shfl(vz, pa);
+                }
                 bool fl = false;
                 if (depth >= k) {
                     fl = encounter(dx, dy, dz, dvx, dvy, dvz, rk, tau);
                     depth = fl ? k + 1 : k;
                 }
                 deeper = __ballot(fl) != 0;
-                // each body's deepest level, over its pairs
-                bd = 0;
+                // each body's deepest level, over its pairs.  With one pair
+                // tested, only its bodies can change: every other pair is
+                // shallower than k, so theirs is that pair's new level
                 unsigned long long rest = mine;
+                if (one) {
+                    if (l == ia1 || l == ib1) bd = lane_int(depth, t1);
+                    rest = 0ull;
+                } else {
+                    bd = 0;
+                }
                 while (__ballot(rest != 0ull)) {
                     const bool have = rest != 0ull;
                     const int t = have ? __builtin_ctzll(rest) : l;
