@@ -389,7 +389,7 @@ __device__ bool load_group(const EncDesc &e, GroupLds &G, int g, bool full) {
 // >= R_{k-1}, or at r <= R_{k+1} below the deepest level, has W_k = 0 and
 // W_k' = 0 exactly (both changeovers clip to the same end), so its force is
 // an exact zero and is not evaluated.
-__device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
+__device__ __forceinline__ void kick(GroupLds &G, int k, double dt, bool reuse) {
 #pragma clang fp contract(off)
     const int nb = G.nb, np = G.np;
     for (int b = lane(); b < nb; b += kGroupThreads) {
@@ -441,7 +441,7 @@ __device__ void kick(GroupLds &G, int k, double dt, bool reuse) {
 
 // The test of level k over tau on the level's pairs: flagged pairs go to
 // level k + 1, the others stay at k.  Returns whether any was flagged.
-__device__ bool check(GroupLds &G, int k, double tau) {
+__device__ __forceinline__ bool check(GroupLds &G, int k, double tau) {
     bool any = false;
     for (int t = lane(); t < G.np; t += kGroupThreads) {
         if (G.depth[t] < k) continue;
@@ -464,7 +464,7 @@ __device__ bool check(GroupLds &G, int k, double tau) {
 
 // Kepler drift for tau of the bodies whose deepest pair is at level k
 // (exactly k, or at least k when `at_least`).
-__device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
+__device__ __forceinline__ void drift(GroupLds &G, int k, double tau, bool at_least) {
     const int nb = G.nb;
     for (int b = lane(); b < nb; b += kGroupThreads) {
         const int d = G.bdepth[b];
@@ -484,7 +484,7 @@ __device__ void drift(GroupLds &G, int k, double tau, bool at_least) {
 // The group's drift over h: M substeps of level 1, each recursing as deep as
 // its pairs need.  The loop visits (level, substep) in the order of the
 // recursion; every wave reaches its end after at most sum_k M^k substeps.
-__device__ void integrate(GroupLds &G, double h) {
+__device__ __forceinline__ void integrate(GroupLds &G, double h) {
     unsigned subs = 0;  // substeps done at each level, two bits per level (M = 4)
     int k = 1;
     bool enter = true;
@@ -583,10 +583,8 @@ __device__ __forceinline__ double swap_pair(double v) {
 // body j in the odd ones (every lane pair holds the same two), each lane
 // reading its partner through a lane swap instead of LDS.  The same
 // operations on the same values as the LDS routines (kick, check, drift with
-// a single pair), so the same bits.  Not inlined: this form and the
-// small-group one each get their own register allocation and schedule
-// (inlined together, a change to one moved the other's substep time).
-__device__ __noinline__ void drift_pair(const EncDesc &e, int g) {
+// a single pair), so the same bits.
+__device__ __forceinline__ void drift_pair(const EncDesc &e, int g) {
 #pragma clang fp contract(off)
     const int p = e.gp[e.gstart[g]];
     const bool first = (lane() & 1) == 0;
@@ -711,8 +709,8 @@ __device__ __noinline__ void drift_pair(const EncDesc &e, int g) {
 // at once; the drifts on every body at once.  While a single pair is at the
 // current level or deeper, its two bodies are read with lane-uniform reads
 // and only they can change level.  The same operations on the same values as
-// the LDS routines, so the same bits.  Not inlined, like drift_pair.
-__device__ __noinline__ void integrate_small(const EncDesc &e, GroupLds &G) {
+// the LDS routines, so the same bits.
+__device__ __forceinline__ void integrate_small(const EncDesc &e, GroupLds &G) {
 #pragma clang fp contract(off)
     const int l = lane(), nb = G.nb, np = G.np;
     const bool isb = l < nb, isp = l < np;
@@ -914,17 +912,27 @@ __device__ __noinline__ void integrate_small(const EncDesc &e, GroupLds &G) {
     wave_sync();
 }
 
+// The two register forms as functions of their own, for the group kernel:
+// each gets its own register allocation and schedule (inlined together, a
+// change to one moved the other's substep time by 4%).  A call gives the
+// kernel a stack in scratch memory, which costs its launch about 1.5 us; the
+// one-block kernel of small problems, launched every step, inlines them.
+__device__ __noinline__ void drift_pair_call(const EncDesc &e, int g) { drift_pair(e, g); }
+__device__ __noinline__ void integrate_small_call(const EncDesc &e, GroupLds &G) { integrate_small(e, G); }
+
 // One group's drift over the step, from its bodies in memory back to them
 // (the table marked them, so the drift kernels left them alone).  One wave.
+// Every form and both ways of calling them give the same bits.
+template <bool kCall>
 __device__ void drift_group(const EncDesc &e, GroupLds &G, int g) {
     if (e.gskip[g]) return;
     if (e.regs && e.gstart[g + 1] - e.gstart[g] == 1) {
-        drift_pair(e, g);
+        if (kCall) drift_pair_call(e, g); else drift_pair(e, g);
         return;
     }
     if (!load_group(e, G, g, true)) return;
     if (e.regs && G.nb <= kGroupThreads && G.np <= kGroupThreads) {
-        integrate_small(e, G);
+        if (kCall) integrate_small_call(e, G); else integrate_small(e, G);
         return;
     }
     integrate(G, e.h);
@@ -953,7 +961,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_enc_groups(const EncDesc e) {
         if (lane() == 0) g = atomicAdd(e.ctl + kEncCtlClaim, 1);
         g = __shfl(g, 0);
         if (g >= ng) break;
-        drift_group(e, G, g);
+        drift_group<true>(e, G, g);
     }
 }
 
@@ -1002,7 +1010,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_enc_drifts_block(const StepDe
     const int w = threadIdx.x / kWave;
     const int ng = e.ctl[kEncCtlGroups];
     if (w < kFusedGroups)
-        for (int g = w; g < ng; g += kFusedGroups) drift_group(e, U.G[w], g);
+        for (int g = w; g < ng; g += kFusedGroups) drift_group<false>(e, U.G[w], g);
     __syncthreads();  // the groups' bodies are back in memory
     const int64_t k = drift::body_of(one);
     double vx = 0.0, vy = 0.0, vz = 0.0;
