@@ -375,14 +375,21 @@ def test_degenerate_problems_are_the_plain_step(n, n_m):
     enc.close()
 
 
-@pytest.mark.parametrize("case", ["cluster", "flyby", "field"])
+@pytest.mark.parametrize("case", ["cluster", "flyby", "field", "binary", "triple"])
 def test_fused_small_problem_launches_are_bit_identical(case):
     """Problems of one block run the encounter step in two fused launches;
-    the general launches (SYMBA_OPT_ENC_FUSE = 0) give the same bits."""
+    the general launches (SYMBA_OPT_ENC_FUSE = 0) give the same bits.  The
+    fused launch compiles the register forms of the group integration into
+    itself, the general group kernel calls them as functions: the tight
+    binary and triple (every substep at the deepest level) compare the two
+    through tens of thousands of substeps."""
     from paper_2304_07325_amd import binding as B
     if case == "flyby":
         x, v, m = _flyby(sep=0.15)
         s, n_m, h = _state(x, v, m), 2, 0.025
+    elif case in ("binary", "triple"):
+        s = _binary() if case == "binary" else _triple()
+        n_m, h = s["x"].size, 0.05
     else:
         s, h = _cluster(), 0.01
         n_m = 40 if case == "cluster" else 28
